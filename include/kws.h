@@ -1,0 +1,201 @@
+/*
+ * kws.h - C ABI of the MI355X (gfx950) distance-bounded graph keyword search.
+ *
+ * The operation. For a directed graph G = (V, E) whose vertices carry
+ * labels, a query (K, d_max, k) asks for the k best roots r: vertices from
+ * which every keyword t in K is reachable within d_max hops along edge
+ * direction. dist_t(r) is the hop count of a shortest path r -> ... -> v
+ * with v carrying t (or, when the labels form a type tree, carrying t or any
+ * type below t). score(r) = sum of dist_t(r) over K; lower is better; ties
+ * break by ascending vertex id. Each returned root comes with its
+ * per-keyword distances and its answer edges: for every keyword, the path
+ * that starts at r and repeatedly steps to the smallest-id out-neighbour one
+ * hop closer to the keyword; the union of those paths, deduplicated and
+ * sorted by (src, dst).
+ *
+ * Citation: the paper (Dupin, PACMMOD 3(3), 2025) fixes only the notation of
+ * this search in its preamble - the radius d_max, dist, the root filter,
+ * the score scr, the answer-graph generator, the type-tree relations
+ * (SubTypeOf, desc) and the inverted index. No section defines their
+ * semantics; the definition above is the reading this library adopts.
+ *
+ * Conventions.
+ *  - Every call returns a kws_status. On error, outputs are left zeroed and
+ *    nothing needs freeing; kws_last_error() gives a thread-local message.
+ *  - Host pointers are read during the call only; the library copies what
+ *    it keeps. Nothing here takes ownership of caller memory.
+ *  - Calls on one graph handle are serialised internally. Device work runs
+ *    on the handle's stream (its own non-blocking stream unless
+ *    kws_set_stream gave one) and every call returns after that work is done.
+ *  - Vertex ids are int32; edge counts must stay below 2^31 (int32 CSR).
+ */
+#ifndef KWS_H
+#define KWS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KWS_MAX_KW 64      /* distinct keywords per query (one 64-bit mask word) */
+#define KWS_MAX_DMAX 15    /* largest supported radius */
+#define KWS_MAX_K 65536    /* largest supported k */
+#define KWS_DIST_INF 255   /* distance value meaning "not within d_max" */
+
+typedef enum {
+  KWS_OK = 0,
+  KWS_EINVAL = -1,      /* malformed input or argument out of range */
+  KWS_ENOMEM = -2,      /* device or host allocation failed / over the memory cap */
+  KWS_EDEVICE = -3,     /* a HIP call or kernel failed */
+  KWS_EOVERFLOW = -4,   /* m >= 2^31 or a size that does not fit int32 */
+  KWS_EBUSY = -5,       /* server admission queue full */
+  KWS_ECANCELLED = -6   /* ticket cancelled */
+} kws_status;
+
+typedef struct kws_graph kws_graph;   /* opaque; owns its device copies */
+
+/* Graph description (all host pointers, read during kws_load_graph only).
+ *  row_ptr[n+1], col[m]: forward CSR, out-neighbours of u are
+ *      col[row_ptr[u] .. row_ptr[u+1]). row_ptr[0] = 0, non-decreasing,
+ *      row_ptr[n] = m; 0 <= col[e] < n. Self-loops and repeated edges are
+ *      allowed (they change no distance).
+ *  lab_ptr[n+1], lab[]: label ids of each vertex, 0 <= lab[i] < n_labels.
+ *  type_parent[n_labels] or NULL: NULL = flat labels (a keyword matches its
+ *      own label only). Otherwise label ids are types of a forest,
+ *      type_parent[t] = parent type or -1; a keyword t then matches t and
+ *      every type below it. Must be acyclic. */
+typedef struct {
+  int32_t n;
+  int64_t m;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  int32_t n_labels;
+  const int32_t *lab_ptr;
+  const int32_t *lab;
+  const int32_t *type_parent;
+} kws_graph_desc;
+
+/* Validates and copies the graph to the device, builds the reverse CSR,
+ * the label inverted index (keyed by type preorder, so a type and its
+ * descendants form one contiguous slice) and the pull degree bins.
+ * EINVAL on malformed input, EOVERFLOW if m >= 2^31, ENOMEM, EDEVICE. */
+kws_status kws_load_graph(const kws_graph_desc *desc, kws_graph **out);
+void kws_free_graph(kws_graph *g);
+
+/* A query: kw[n_kw] keyword (label) ids, duplicates allowed and removed;
+ * 1 <= distinct count <= KWS_MAX_KW; 0 <= d_max <= KWS_MAX_DMAX;
+ * 0 <= k <= KWS_MAX_K. */
+typedef struct {
+  const int32_t *kw;
+  int32_t n_kw;
+  int32_t d_max;
+  int32_t k;
+} kws_query;
+
+/* A result, allocated by the library; release with kws_result_free.
+ *  kw[n_kw]           distinct keywords, ascending (the column order of kw_dist)
+ *  roots[n_roots]     n_roots = min(k, number of qualifying roots), ordered by
+ *  scores[n_roots]      (score ascending, vertex id ascending)
+ *  kw_dist[n_roots*n_kw]  row i: dist of roots[i] to each keyword
+ *  edge_ptr[n_roots+1], edge_src/edge_dst[edge_ptr[n_roots]]: answer edges
+ *      of roots[i] are entries edge_ptr[i] .. edge_ptr[i+1]-1, sorted (src,dst).
+ *  te                 reverse edges a plain per-keyword BFS would scan for
+ *                     this query (in-degrees of vertices at dist < d_max,
+ *                     summed over keywords): the GTEPS numerator. */
+typedef struct {
+  int32_t n_roots;
+  int32_t n_kw;
+  int32_t *kw;
+  int32_t *roots;
+  int32_t *scores;
+  uint8_t *kw_dist;
+  int64_t *edge_ptr;
+  int32_t *edge_src;
+  int32_t *edge_dst;
+  int64_t te;
+} kws_result;
+
+/* Plain path: one query per call, one mask word. */
+kws_status kws_keyword_search(kws_graph *g, const kws_query *q, kws_result *out);
+
+/* Batched path: nq queries of uneven keyword count and d_max in one device
+ * pass (lanes packed into 64-bit mask words). out[nq] receives one result
+ * per query, identical to what kws_keyword_search returns for it. */
+kws_status kws_search_batch(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out);
+
+void kws_result_free(kws_result *r);
+
+/* Verification: dist_n[n] = truncated distance of every vertex to keyword
+ * kw (KWS_DIST_INF beyond d_max), computed by the same device kernels. */
+kws_status kws_debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist_n);
+
+/* Engine options. Zero fields mean "default". */
+typedef struct {
+  int32_t direction;     /* 0 auto (device-side choice), 1 always push, 2 always pull */
+  float alpha;           /* pull when alpha * frontier_in_edges > unfinished_out_edges */
+  int32_t tile_words;    /* words per vertex per tile: 1, 2, 4, 8 or 16 */
+  int32_t block;         /* threads per workgroup for the streaming kernels: 64..1024 */
+  int32_t use_graph;     /* 1: capture each batch shape once in a hipGraph and replay it */
+  int32_t share_lanes;   /* 1 (default): queries in one word share equal (keyword, d_max) lanes; -1: off */
+} kws_options;
+kws_status kws_set_options(kws_graph *g, const kws_options *opt);
+kws_status kws_get_options(kws_graph *g, kws_options *opt);
+
+/* Runs device work on this stream (a hipStream_t, e.g. from
+ * torch.cuda.Stream().cuda_stream). NULL restores the handle's own stream.
+ * The stream must be a default-priority stream. */
+kws_status kws_set_stream(kws_graph *g, void *hip_stream);
+void *kws_get_stream(kws_graph *g);
+
+/* Device memory hooks (e.g. PyTorch's caching allocator). Process-wide;
+ * set before loading graphs. alloc returns NULL on failure. NULL hooks
+ * restore hipMalloc/hipFree. */
+typedef void *(*kws_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*kws_free_fn)(void *ptr, void *ctx);
+kws_status kws_set_allocator(kws_alloc_fn alloc, kws_free_fn free_, void *ctx);
+
+/* Graph facts. */
+typedef struct {
+  int32_t n;
+  int64_t m;
+  int32_t n_labels;
+  int32_t hierarchical;
+  int64_t device_bytes;   /* graph store bytes on the device */
+  int32_t max_out_degree;
+  int32_t max_in_degree;
+} kws_graph_info;
+kws_status kws_graph_info_get(kws_graph *g, kws_graph_info *info);
+
+/* Per-kernel timing with HIP events on the handle's stream. While enabled
+ * each launch is bracketed by events; kws_profile_read returns, for kernel
+ * class id, the number of launches and their summed duration (ms) since
+ * the last reset. kws_profile_name gives the class name (NULL past the end). */
+kws_status kws_profile_enable(kws_graph *g, int32_t on);
+kws_status kws_profile_reset(kws_graph *g);
+kws_status kws_profile_read(kws_graph *g, int32_t id, int64_t *launches, double *total_ms);
+const char *kws_profile_name(int32_t id);
+
+/* Statistics of the last batch: lanes, words, per-level direction. */
+typedef struct {
+  int32_t queries;
+  int32_t lanes;           /* distinct (keyword, d_max) lanes after sharing */
+  int32_t lane_slots;      /* sum of per-query distinct keyword counts */
+  int32_t words;
+  int32_t tiles;
+  int32_t tile_words;
+  int32_t levels;
+  int32_t pulled[KWS_MAX_DMAX];     /* 1 if level l expanded by pull */
+  int64_t frontier[KWS_MAX_DMAX];   /* frontier vertices entering level l */
+  int64_t frontier_edges[KWS_MAX_DMAX];
+} kws_batch_stats;
+kws_status kws_last_batch_stats(kws_graph *g, kws_batch_stats *st);
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char *kws_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KWS_H */

@@ -1,0 +1,338 @@
+// C ABI entry points, error reporting, device/host buffers and the profiler.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "kws_internal.h"
+
+namespace kws {
+
+// ---------------------------------------------------------------- errors
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+kws_status fail(kws_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+// ---------------------------------------------------------------- memory
+namespace {
+kws_alloc_fn g_alloc = nullptr;
+kws_free_fn g_free = nullptr;
+void *g_ctx = nullptr;
+std::mutex g_mem_mu;
+std::atomic<int64_t> g_dev_bytes{0};
+int64_t g_mem_limit = -1;   // KWS_MEM_LIMIT_BYTES, -1 = unlimited
+bool g_limit_read = false;
+std::vector<std::pair<void *, size_t>> g_live;   // allocations and their sizes
+
+int64_t mem_limit() {
+  if (!g_limit_read) {
+    const char *e = getenv("KWS_MEM_LIMIT_BYTES");
+    g_mem_limit = e ? atoll(e) : -1;
+    g_limit_read = true;
+  }
+  return g_mem_limit;
+}
+}  // namespace
+
+void *dev_alloc(size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  const int64_t lim = mem_limit();
+  if (lim >= 0 && g_dev_bytes.load() + (int64_t)bytes > lim) return nullptr;
+  void *p = nullptr;
+  if (g_alloc) {
+    p = g_alloc(bytes, g_ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    hipGetLastError();
+    p = nullptr;
+  }
+  if (p) {
+    g_dev_bytes += (int64_t)bytes;
+    g_live.push_back({p, bytes});
+  }
+  return p;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  for (size_t i = 0; i < g_live.size(); i++)
+    if (g_live[i].first == p) {
+      g_dev_bytes -= (int64_t)g_live[i].second;
+      g_live[i] = g_live.back();
+      g_live.pop_back();
+      break;
+    }
+  if (g_free) g_free(p, g_ctx);
+  else hipFree(p);
+}
+
+int64_t dev_bytes_in_use() { return g_dev_bytes.load(); }
+
+kws_status DevBuf::ensure(size_t want, const char *what) {
+  if (want <= bytes && p) return KWS_OK;
+  release();
+  size_t b = std::max<size_t>(want, 256);
+  p = dev_alloc(b);
+  if (!p) return fail(KWS_ENOMEM, "device allocation of %zu bytes for %s failed", b, what);
+  bytes = b;
+  return KWS_OK;
+}
+
+void DevBuf::release() {
+  dev_free(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+kws_status HostBuf::ensure(size_t want, const char *what) {
+  if (want <= bytes && p) return KWS_OK;
+  release();
+  size_t b = std::max<size_t>(want, 4096);
+  b += b / 4;
+  if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+    hipGetLastError();
+    p = nullptr;
+    return fail(KWS_ENOMEM, "pinned host allocation of %zu bytes for %s failed", b, what);
+  }
+  bytes = b;
+  return KWS_OK;
+}
+
+void HostBuf::release() {
+  if (p) hipHostFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void Engine::release() {
+  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &plan, &zero_region,
+                 &qsel, &work, &cand, &arena};
+  for (DevBuf *b : d) b->release();
+  h_plan.release();
+  h_arena.release();
+  state_words = 0;
+}
+
+// ---------------------------------------------------------------- profiler
+const char *kernel_class_name(int id) {
+  static const char *names[KC_COUNT] = {"seed", "push", "pull", "finalize", "score", "threshold",
+                                        "select", "finish", "answer", "export", "build"};
+  return id >= 0 && id < KC_COUNT ? names[id] : nullptr;
+}
+
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::begin(int cls, hipStream_t s, hipEvent_t *a) {
+  (void)cls;
+  *a = nullptr;
+  if (!on) return;
+  *a = get();
+  if (*a) hipEventRecord(*a, s);
+}
+
+void Profiler::end(int cls, hipStream_t s, hipEvent_t a) {
+  if (!on || !a) return;
+  hipEvent_t b = get();
+  if (!b) return;
+  hipEventRecord(b, s);
+  pending.push_back({cls, a, b});
+}
+
+kws_status Profiler::collect() {
+  for (auto &p : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      launches[p.cls]++;
+      total_ms[p.cls] += ms;
+    }
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pending.clear();
+  return KWS_OK;
+}
+
+void Profiler::reset() {
+  for (int i = 0; i < KC_COUNT; i++) { launches[i] = 0; total_ms[i] = 0; }
+}
+
+void Profiler::release() {
+  for (auto &p : pending) { pool.push_back(p.a); pool.push_back(p.b); }
+  pending.clear();
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+  pool.clear();
+}
+
+}  // namespace kws
+
+// ================================================================ C ABI
+extern "C" {
+
+const char *kws_last_error(void) { return kws::g_err; }
+
+kws_status kws_set_allocator(kws_alloc_fn alloc, kws_free_fn free_, void *ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return kws::fail(KWS_EINVAL, "set both allocator hooks or neither");
+  std::lock_guard<std::mutex> lk(kws::g_mem_mu);
+  if (!kws::g_live.empty()) return kws::fail(KWS_EBUSY, "device allocations are live; set hooks first");
+  kws::g_alloc = alloc;
+  kws::g_free = free_;
+  kws::g_ctx = ctx;
+  return KWS_OK;
+}
+
+kws_status kws_load_graph(const kws_graph_desc *desc, kws_graph **out) {
+  kws::clear_error();
+  kws_status st = kws::load_graph(desc, out);
+  if (st != KWS_OK) return st;
+  kws_graph *g = *out;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    hipGetLastError();
+    free_b = 0;
+  }
+  size_t budget = (size_t)((double)free_b * 0.85);
+  const int64_t lim = kws::mem_limit();
+  if (lim >= 0) {
+    const int64_t left = lim - kws::dev_bytes_in_use();
+    budget = std::min<size_t>(budget ? budget : (size_t)left, (size_t)std::max<int64_t>(left, 0));
+  }
+  g->mem_budget = budget;
+  return KWS_OK;
+}
+
+void kws_free_graph(kws_graph *g) { kws::free_graph(g); }
+
+kws_status kws_keyword_search(kws_graph *g, const kws_query *q, kws_result *out) {
+  kws::clear_error();
+  if (!g || !q || !out) return kws::fail(KWS_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(g->mu);
+  return kws::search(g, q, 1, out);
+}
+
+kws_status kws_search_batch(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out) {
+  kws::clear_error();
+  if (!g) return kws::fail(KWS_EINVAL, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  return kws::search(g, qs, nq, out);
+}
+
+void kws_result_free(kws_result *r) {
+  if (!r) return;
+  free(r->kw); free(r->roots); free(r->scores); free(r->kw_dist);
+  free(r->edge_ptr); free(r->edge_src); free(r->edge_dst);
+  memset(r, 0, sizeof(*r));
+}
+
+kws_status kws_debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist_n) {
+  kws::clear_error();
+  if (!g) return kws::fail(KWS_EINVAL, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  return kws::debug_distances(g, kw, d_max, dist_n);
+}
+
+kws_status kws_set_options(kws_graph *g, const kws_options *opt) {
+  if (!g || !opt) return kws::fail(KWS_EINVAL, "null argument");
+  kws_options o;
+  kws::default_options(&o);
+  if (opt->direction < 0 || opt->direction > 2) return kws::fail(KWS_EINVAL, "direction must be 0, 1 or 2");
+  o.direction = opt->direction;
+  if (opt->alpha < 0) return kws::fail(KWS_EINVAL, "alpha must be >= 0");
+  if (opt->alpha > 0) o.alpha = opt->alpha;
+  if (opt->tile_words) {
+    const int t = opt->tile_words;
+    if (t != 1 && t != 2 && t != 4 && t != 8 && t != 16) return kws::fail(KWS_EINVAL, "tile_words must be 1, 2, 4, 8 or 16");
+    o.tile_words = t;
+  }
+  if (opt->block && opt->block != kws::BLOCK) return kws::fail(KWS_EINVAL, "block must be %d", kws::BLOCK);
+  o.use_graph = opt->use_graph > 0 ? 1 : 0;
+  o.share_lanes = opt->share_lanes < 0 ? -1 : 1;
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->opt = o;
+  return KWS_OK;
+}
+
+kws_status kws_get_options(kws_graph *g, kws_options *opt) {
+  if (!g || !opt) return kws::fail(KWS_EINVAL, "null argument");
+  *opt = g->opt;
+  return KWS_OK;
+}
+
+kws_status kws_set_stream(kws_graph *g, void *hip_stream) {
+  if (!g) return kws::fail(KWS_EINVAL, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  if (g->stream) hipStreamSynchronize(g->stream);
+  g->stream = hip_stream ? (hipStream_t)hip_stream : g->own_stream;
+  return KWS_OK;
+}
+
+void *kws_get_stream(kws_graph *g) { return g ? (void *)g->stream : nullptr; }
+
+kws_status kws_graph_info_get(kws_graph *g, kws_graph_info *info) {
+  if (!g || !info) return kws::fail(KWS_EINVAL, "null argument");
+  info->n = g->n;
+  info->m = g->m;
+  info->n_labels = g->n_labels;
+  info->hierarchical = g->hier ? 1 : 0;
+  info->device_bytes = g->device_bytes;
+  info->max_out_degree = g->max_out;
+  info->max_in_degree = g->max_in;
+  return KWS_OK;
+}
+
+kws_status kws_profile_enable(kws_graph *g, int32_t on) {
+  if (!g) return kws::fail(KWS_EINVAL, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->prof.on = on != 0;
+  return KWS_OK;
+}
+
+kws_status kws_profile_reset(kws_graph *g) {
+  if (!g) return kws::fail(KWS_EINVAL, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->prof.reset();
+  return KWS_OK;
+}
+
+kws_status kws_profile_read(kws_graph *g, int32_t id, int64_t *launches, double *total_ms) {
+  if (!g || !launches || !total_ms) return kws::fail(KWS_EINVAL, "null argument");
+  if (id < 0 || id >= kws::KC_COUNT) return kws::fail(KWS_EINVAL, "no kernel class %d", id);
+  std::lock_guard<std::mutex> lk(g->mu);
+  *launches = g->prof.launches[id];
+  *total_ms = g->prof.total_ms[id];
+  return KWS_OK;
+}
+
+const char *kws_profile_name(int32_t id) { return kws::kernel_class_name(id); }
+
+kws_status kws_last_batch_stats(kws_graph *g, kws_batch_stats *st) {
+  if (!g || !st) return kws::fail(KWS_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(g->mu);
+  *st = g->last;
+  return KWS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal declarations of the keyword-search library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kws.h"
+
+namespace kws {
+
+// ---------------------------------------------------------------- errors
+kws_status fail(kws_status st, const char *fmt, ...);
+void clear_error();
+
+#define KWS_HIP(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::kws::fail(KWS_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                         __FILE__, __LINE__);                                            \
+  } while (0)
+
+#define KWS_TRY(expr)                       \
+  do {                                      \
+    kws_status s_ = (expr);                 \
+    if (s_ != KWS_OK) return s_;            \
+  } while (0)
+
+// ---------------------------------------------------------------- memory
+void *dev_alloc(size_t bytes);   // hooks or hipMalloc; nullptr on failure
+void dev_free(void *p);
+
+// A device buffer that only grows.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  kws_status ensure(size_t want, const char *what);
+  void release();
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// A pinned host buffer that only grows.
+struct HostBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  kws_status ensure(size_t want, const char *what);
+  void release();
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------- profiling
+enum KernelClass {
+  KC_SEED = 0, KC_PUSH, KC_PULL, KC_FINALIZE, KC_SCORE, KC_THRESHOLD, KC_SELECT,
+  KC_FINISH, KC_ANSWER, KC_EXPORT, KC_BUILD, KC_COUNT
+};
+const char *kernel_class_name(int id);
+
+struct Profiler {
+  bool on = false;
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[KC_COUNT] = {};
+  double total_ms[KC_COUNT] = {};
+  hipEvent_t get();
+  void begin(int cls, hipStream_t s, hipEvent_t *a);
+  void end(int cls, hipStream_t s, hipEvent_t a);
+  kws_status collect();   // after the stream is synchronised
+  void reset();
+  void release();
+};
+
+// ---------------------------------------------------------------- pull bins
+// Vertices are grouped by out-degree so each group of threads gets a row of
+// a size it handles well. Hub rows are cut into fixed-size edge chunks that
+// merge their partial OR with atomics.
+enum { BIN_SMALL = 0, BIN_MEDIUM, BIN_LARGE, BIN_COUNT };
+constexpr int32_t BIN_SMALL_MAX = 8;
+constexpr int32_t BIN_MEDIUM_MAX = 128;
+constexpr int32_t BIN_LARGE_MAX = 4096;
+constexpr int32_t HUB_CHUNK = 4096;
+
+constexpr int MAX_WORDS = 1024;      // words per device pass (65536 lanes)
+constexpr int BLOCK = 256;
+
+// ---------------------------------------------------------------- engine state
+struct Engine {
+  // search state, layout [tile][vertex][T words], sized for the largest pass
+  DevBuf vis, fr0, fr1, nxt, planes;   // planes: [4][tiles][n][T]
+  size_t state_words = 0;              // words per array currently allocated (n * Wp)
+  DevBuf flist, flist_eoff;            // frontier list and in-edge offsets
+  DevBuf plan;                         // per-pass plan (device copy)
+  DevBuf zero_region;                  // per-pass counters zeroed by the seed kernel
+  DevBuf qsel;                         // per-query top-k threshold
+  DevBuf work;                         // select work items
+  DevBuf cand;                         // top-k candidates
+  DevBuf arena;                        // results (one D2H copy)
+  HostBuf h_plan, h_arena;
+  hipEvent_t done_event = nullptr;
+  void release();
+};
+
+// graph-capture cache entry
+struct GraphEntry {
+  std::vector<uint8_t> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace kws
+
+struct kws_graph {
+  int device = 0;
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t n_labels = 0;
+  bool hier = false;
+  // device graph store
+  int32_t *fwd_ptr = nullptr, *fwd_col = nullptr;
+  int32_t *rev_ptr = nullptr, *rev_col = nullptr;
+  int32_t *inv_ptr = nullptr, *inv_vtx = nullptr;    // by preorder key
+  int32_t *bin_vtx = nullptr;                        // vertices of the pull bins
+  int32_t *hub_v = nullptr, *hub_b = nullptr, *hub_e = nullptr;
+  int64_t bin_begin[kws::BIN_COUNT + 1] = {};
+  int64_t n_hub = 0;
+  // host mirrors used for planning
+  std::vector<int32_t> pre, span;                    // type preorder key and subtree size
+  std::vector<int32_t> h_inv_ptr;                    // [n_labels + 1]
+  int32_t max_out = 0, max_in = 0;
+  int64_t device_bytes = 0;
+  // execution
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  kws_options opt{};
+  kws::Engine eng;
+  kws::Profiler prof;
+  kws_batch_stats last{};
+  std::vector<kws::GraphEntry> graphs;
+  size_t mem_budget = 0;                             // bytes allowed for search state
+};
+
+namespace kws {
+kws_status load_graph(const kws_graph_desc *d, kws_graph **out);
+void free_graph(kws_graph *g);
+void default_options(kws_options *o);
+kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out);
+kws_status debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist);
+}  // namespace kws

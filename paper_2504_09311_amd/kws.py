@@ -1,0 +1,302 @@
+"""Thin ctypes binding of ``libkws.so`` (declared in ``include/kws.h``).
+
+Argument marshalling only: every step of a search runs in the library's
+HIP kernels. The names follow the C entry points without the ``kws_``
+prefix. Importing this module never falls back to anything else: if the
+built library is missing, ``load_library`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkws.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EBUSY, ECANCELLED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "EBUSY",
+                -6: "ECANCELLED"}
+MAX_KW, MAX_DMAX, MAX_K, DIST_INF = 64, 15, 65536, 255
+MAX_LEVELS = 15
+
+
+class KwsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("n_labels", C.c_int32), ("lab_ptr", C.c_void_p), ("lab", C.c_void_p),
+                ("type_parent", C.c_void_p)]
+
+
+class QueryC(C.Structure):
+    _fields_ = [("kw", C.c_void_p), ("n_kw", C.c_int32), ("d_max", C.c_int32), ("k", C.c_int32)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("n_roots", C.c_int32), ("n_kw", C.c_int32), ("kw", C.POINTER(C.c_int32)),
+                ("roots", C.POINTER(C.c_int32)), ("scores", C.POINTER(C.c_int32)),
+                ("kw_dist", C.POINTER(C.c_uint8)), ("edge_ptr", C.POINTER(C.c_int64)),
+                ("edge_src", C.POINTER(C.c_int32)), ("edge_dst", C.POINTER(C.c_int32)),
+                ("te", C.c_int64)]
+
+
+class Options(C.Structure):
+    _fields_ = [("direction", C.c_int32), ("alpha", C.c_float), ("tile_words", C.c_int32),
+                ("block", C.c_int32), ("use_graph", C.c_int32), ("share_lanes", C.c_int32)]
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int64), ("n_labels", C.c_int32), ("hierarchical", C.c_int32),
+                ("device_bytes", C.c_int64), ("max_out_degree", C.c_int32), ("max_in_degree", C.c_int32)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("queries", C.c_int32), ("lanes", C.c_int32), ("lane_slots", C.c_int32),
+                ("words", C.c_int32), ("tiles", C.c_int32), ("tile_words", C.c_int32),
+                ("levels", C.c_int32), ("pulled", C.c_int32 * MAX_LEVELS),
+                ("frontier", C.c_int64 * MAX_LEVELS), ("frontier_edges", C.c_int64 * MAX_LEVELS)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2504_09311_amd/build.py "
+                           "(or __graft_entry__.build()) before use")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    sigs = {
+        "kws_load_graph": (C.c_int, [C.POINTER(GraphDesc), C.POINTER(P)]),
+        "kws_free_graph": (None, [P]),
+        "kws_keyword_search": (C.c_int, [P, C.POINTER(QueryC), C.POINTER(ResultC)]),
+        "kws_search_batch": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.POINTER(ResultC)]),
+        "kws_result_free": (None, [C.POINTER(ResultC)]),
+        "kws_debug_distances": (C.c_int, [P, C.c_int32, C.c_int32, P]),
+        "kws_set_options": (C.c_int, [P, C.POINTER(Options)]),
+        "kws_get_options": (C.c_int, [P, C.POINTER(Options)]),
+        "kws_set_stream": (C.c_int, [P, P]),
+        "kws_get_stream": (P, [P]),
+        "kws_set_allocator": (C.c_int, [P, P, P]),
+        "kws_graph_info_get": (C.c_int, [P, C.POINTER(GraphInfo)]),
+        "kws_profile_enable": (C.c_int, [P, C.c_int32]),
+        "kws_profile_reset": (C.c_int, [P]),
+        "kws_profile_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+        "kws_profile_name": (C.c_char_p, [C.c_int32]),
+        "kws_last_batch_stats": (C.c_int, [P, C.POINTER(BatchStats)]),
+        "kws_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols() -> List[str]:
+    """The function names include/kws.h declares (parsed from the header)."""
+    import re
+    hdr = os.path.join(os.path.dirname(HERE), "include", "kws.h")
+    text = open(hdr).read()
+    return sorted(set(re.findall(r"\b(kws_[a-z_]+)\s*\(", text)))
+
+
+def last_error() -> str:
+    return (load_library().kws_last_error() or b"").decode()
+
+
+def _check(st: int):
+    if st != OK:
+        raise KwsError(st, last_error())
+
+
+@dataclass
+class Result:
+    """One query's answer (same fields as the C kws_result, as numpy arrays)."""
+    kw: List[int]
+    roots: np.ndarray
+    scores: np.ndarray
+    kw_dist: np.ndarray
+    edge_ptr: np.ndarray
+    edge_src: np.ndarray
+    edge_dst: np.ndarray
+    te: int
+
+    def edges_of(self, i: int):
+        a, b = int(self.edge_ptr[i]), int(self.edge_ptr[i + 1])
+        return list(zip(self.edge_src[a:b].tolist(), self.edge_dst[a:b].tolist()))
+
+
+def _take(r: ResultC) -> Result:
+    nr, nk = r.n_roots, r.n_kw
+    ne = int(r.edge_ptr[nr]) if r.edge_ptr else 0
+
+    def arr(ptr, count, dt):
+        if count == 0 or not ptr:
+            return np.zeros(0, dt)
+        return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+    return Result([int(x) for x in arr(r.kw, nk, np.int32)], arr(r.roots, nr, np.int32),
+                  arr(r.scores, nr, np.int32), arr(r.kw_dist, nr * nk, np.uint8).reshape(nr, nk),
+                  arr(r.edge_ptr, nr + 1, np.int64), arr(r.edge_src, ne, np.int32),
+                  arr(r.edge_dst, ne, np.int32), int(r.te))
+
+
+def _queries(qs) -> tuple:
+    keep, arr = [], (QueryC * max(1, len(qs)))()
+    for i, q in enumerate(qs):
+        kw, d_max, k = (q.kw, q.d_max, q.k) if hasattr(q, "kw") else q
+        a = np.ascontiguousarray(np.asarray(kw, np.int32))
+        keep.append(a)
+        arr[i].kw = a.ctypes.data if a.size else None
+        arr[i].n_kw = int(a.size)
+        arr[i].d_max = int(d_max)
+        arr[i].k = int(k)
+    return arr, keep
+
+
+class Graph:
+    """A graph resident on the device (wraps a kws_graph handle)."""
+
+    def __init__(self, row_ptr, col, n_labels: int, lab_ptr, lab, type_parent=None):
+        lib = load_library()
+        self._lib = lib
+        self._arrs = [np.ascontiguousarray(np.asarray(x, np.int32)) for x in (row_ptr, col, lab_ptr, lab)]
+        rp, cl, lp, lb = self._arrs
+        tp = None
+        if type_parent is not None:
+            tp = np.ascontiguousarray(np.asarray(type_parent, np.int32))
+            self._arrs.append(tp)
+        d = GraphDesc(int(rp.shape[0] - 1), int(cl.shape[0]), rp.ctypes.data, cl.ctypes.data if cl.size else None,
+                      int(n_labels), lp.ctypes.data, lb.ctypes.data if lb.size else None,
+                      tp.ctypes.data if tp is not None else None)
+        h = C.c_void_p()
+        _check(lib.kws_load_graph(C.byref(d), C.byref(h)))
+        self.h = h
+        self._arrs = None          # the library keeps its own copies
+
+    @classmethod
+    def from_synth(cls, g) -> "Graph":
+        return cls(g.row_ptr, g.col, g.n_labels, g.lab_ptr, g.lab, g.type_parent)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.kws_free_graph(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- searches
+    def keyword_search(self, kw: Sequence[int], d_max: int, k: int) -> Result:
+        qa, keep = _queries([(kw, d_max, k)])
+        r = ResultC()
+        _check(self._lib.kws_keyword_search(self.h, qa, C.byref(r)))
+        try:
+            return _take(r)
+        finally:
+            self._lib.kws_result_free(C.byref(r))
+
+    def search_batch(self, queries) -> List[Result]:
+        qa, keep = _queries(queries)
+        n = len(queries)
+        rs = (ResultC * max(1, n))()
+        _check(self._lib.kws_search_batch(self.h, qa, n, rs))
+        try:
+            return [_take(rs[i]) for i in range(n)]
+        finally:
+            for i in range(n):
+                self._lib.kws_result_free(C.byref(rs[i]))
+
+    def debug_distances(self, kw: int, d_max: int) -> np.ndarray:
+        n = self.info().n
+        out = np.empty(n, np.uint8)
+        _check(self._lib.kws_debug_distances(self.h, int(kw), int(d_max), out.ctypes.data))
+        return out
+
+    # ---- configuration and introspection
+    def set_options(self, direction: int = 0, alpha: float = 0.0, tile_words: int = 0, use_graph: int = 0,
+                    share_lanes: int = 0):
+        o = Options(direction, alpha, tile_words, 0, use_graph, share_lanes)
+        _check(self._lib.kws_set_options(self.h, C.byref(o)))
+
+    def get_options(self) -> Options:
+        o = Options()
+        _check(self._lib.kws_get_options(self.h, C.byref(o)))
+        return o
+
+    def set_stream(self, stream_ptr: Optional[int]):
+        _check(self._lib.kws_set_stream(self.h, stream_ptr))
+
+    def get_stream(self) -> int:
+        return int(self._lib.kws_get_stream(self.h) or 0)
+
+    def info(self) -> GraphInfo:
+        i = GraphInfo()
+        _check(self._lib.kws_graph_info_get(self.h, C.byref(i)))
+        return i
+
+    def profile_enable(self, on: bool = True):
+        _check(self._lib.kws_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(self._lib.kws_profile_reset(self.h))
+
+    def profile_read(self) -> dict:
+        out = {}
+        i = 0
+        while True:
+            name = self._lib.kws_profile_name(i)
+            if not name:
+                break
+            n, ms = C.c_int64(), C.c_double()
+            _check(self._lib.kws_profile_read(self.h, i, C.byref(n), C.byref(ms)))
+            out[name.decode()] = (int(n.value), float(ms.value))
+            i += 1
+        return out
+
+    def last_batch_stats(self) -> BatchStats:
+        s = BatchStats()
+        _check(self._lib.kws_last_batch_stats(self.h, C.byref(s)))
+        return s
+
+
+_torch_hooks = None
+
+
+def set_allocator_torch(device: int = 0):
+    """Route the library's device allocations through PyTorch's caching allocator."""
+    import torch
+    global _torch_hooks
+
+    def _alloc(nbytes, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), device))
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    _torch_hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _check(load_library().kws_set_allocator(C.cast(_torch_hooks[0], C.c_void_p),
+                                            C.cast(_torch_hooks[1], C.c_void_p), None))

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact on every field (roots, scores, per-keyword distances, answer
+edges, scanned-edge counts). Covers the plain one-query path and the
+batched path, every tile width, forced push / forced pull / automatic
+direction, lane sharing on and off, hand-derived worked examples,
+hundreds of random tiny graphs with the awkward cases, the small
+Chung-Lu workload, the 2^20-vertex R-MAT workloads (plain query set and
+the 256-query batch), the type-tree workload at reduced scale, and the
+per-keyword distance export checked against the BFS certificate.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from parity import assert_all_same, assert_same, oracle_results
+from synth import tiny, workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def K():
+    import paper_2504_09311_amd as K
+    K.load_library()
+    return K
+
+
+def test_golden_worked_examples(K):
+    spec = json.load(open(GOLDEN))
+    for case in spec["cases"]:
+        g = tiny.from_edges(case["n"], case["edges"], case["labels"], case["n_labels"],
+                            case["type_parent"], case["name"])
+        say("golden", case["name"])
+        G = K.Graph.from_synth(g)
+        for q in case["queries"]:
+            r = G.keyword_search(q["kw"], q["d_max"], q["k"])
+            e = q["expect"]
+            assert r.kw == e["kw"] and r.roots.tolist() == e["roots"]
+            assert r.scores.tolist() == e["scores"] and r.kw_dist.tolist() == e["kw_dist"]
+            assert [[list(x) for x in r.edges_of(i)] for i in range(len(r.roots))] == e["edges"]
+            assert r.te == e["te"]
+        G.close()
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_tiny_random(K, block):
+    for seed in range(block * 50, block * 50 + 50):
+        g = tiny.random_graph(seed)
+        qs = tiny.random_queries(g, seed, 6)
+        o = oracle.Oracle(g)
+        want = [o.search(q.kw, q.d_max, q.k) for q in qs]
+        say("tiny", seed, g.n, g.m, [(q.kw, q.d_max, q.k) for q in qs])
+        G = K.Graph.from_synth(g)
+        for i, q in enumerate(qs):
+            assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"tiny {seed} plain {i}")
+        for direction in (0, 1, 2):
+            G.set_options(direction=direction, tile_words=[1, 2, 4, 8, 16][seed % 5],
+                          share_lanes=1 if seed % 2 else -1)
+            assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction}")
+        G.close()
+
+
+def test_tiny_batch_of_many_words(K):
+    # one small graph, 300 queries: several words, tiles and shared lanes
+    g = tiny.random_graph(7, n_max=48)
+    while g.m == 0:
+        g = tiny.random_graph(g.n + 1000, n_max=48)
+    qs = []
+    for s in range(75):
+        qs += tiny.random_queries(g, 1000 + s, 4)
+    o = oracle.Oracle(g)
+    want = [o.search(q.kw, q.d_max, q.k) for q in qs]
+    G = K.Graph.from_synth(g)
+    for tw in (1, 4, 16):
+        for share in (1, -1):
+            say("many words", tw, share)
+            G.set_options(tile_words=tw, share_lanes=share)
+            assert_all_same(G.search_batch(qs), want, f"many tw {tw} share {share}")
+    G.close()
+
+
+def test_special_graphs(K):
+    for g, kw in [(tiny.path_graph(40), [0]), (tiny.complete_digraph(9, {2, 5}), [0]),
+                  (tiny.no_edges(5, [[0, 1], [1], [], [0, 1, 2], [0]], 3), [1, 0])]:
+        o = oracle.Oracle(g)
+        G = K.Graph.from_synth(g)
+        for d_max in (0, 1, 3, 15):
+            for k in (0, 1, 5, 100):
+                say("special", g.name, d_max, k)
+                assert_same(G.keyword_search(kw, d_max, k), o.search(kw, d_max, k), g.name)
+        G.close()
+
+
+@pytest.fixture(scope="module")
+def chunglu(K):
+    g = workloads.chunglu10k()
+    return g, oracle.Oracle(g), K.Graph.from_synth(g)
+
+
+def test_chunglu10k_plain_and_batch(K, chunglu):
+    g, o, G = chunglu
+    qs = workloads.chunglu10k_queries(101)
+    want = oracle_results(o, qs)
+    say("chunglu10k plain")
+    for i, q in enumerate(qs):
+        assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"chunglu plain {i}")
+    for direction in (0, 1, 2):
+        say("chunglu10k batch", direction)
+        G.set_options(direction=direction)
+        assert_all_same(G.search_batch(qs), want, f"chunglu batch {direction}")
+    G.set_options()
+
+
+def test_chunglu10k_mixed_shapes(K, chunglu):
+    g, o, G = chunglu
+    from synth import gen
+    qs = gen.queries(200, 500, 1.1, 1, 12, [0, 1, 2, 3, 4, 6], 25, 0x5EED0101, 42)
+    want = oracle_results(o, qs)
+    for tw in (1, 2, 8, 16):
+        say("chunglu mixed", tw)
+        G.set_options(tile_words=tw)
+        assert_all_same(G.search_batch(qs), want, f"chunglu mixed tw {tw}")
+    G.set_options()
+
+
+def test_distances_export_certificate(K, chunglu):
+    g, o, G = chunglu
+    for t in (0, 1, 17, 250, 499):
+        for d_max in (0, 2, 5):
+            say("export", t, d_max)
+            d = G.debug_distances(t, d_max)
+            want, _ = o.distances(t, d_max)
+            assert np.array_equal(d, want)
+            assert brute.certificate(g.row_ptr, g.col, o.keyword_set(t), d, d_max) == []
+
+
+@pytest.fixture(scope="module")
+def rmat14(K):
+    g = workloads.rmat_flat(14)
+    return g, oracle.Oracle(g), K.Graph.from_synth(g)
+
+
+def test_rmat14_options_grid(K, rmat14):
+    g, o, G = rmat14
+    qs = workloads.rmat_flat_queries(96, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=3)
+    want = oracle_results(o, qs)
+    for tw in (1, 2, 4, 8, 16):
+        for direction in (0, 1, 2):
+            say("rmat14", tw, direction)
+            G.set_options(direction=direction, tile_words=tw)
+            assert_all_same(G.search_batch(qs), want, f"rmat14 tw {tw} dir {direction}")
+    G.set_options(share_lanes=-1)
+    assert_all_same(G.search_batch(qs), want, "rmat14 no sharing")
+    G.set_options()
+    for i in range(0, 96, 7):
+        assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"rmat14 plain {i}")
+
+
+def test_rmat14_hierarchy(K):
+    g, leaves = workloads.rmat_hier(14, cfg=4)
+    qs = workloads.rmat_hier_queries(g.type_parent, leaves, 64, cfg=4)
+    o = oracle.Oracle(g)
+    want = oracle_results(o, qs)
+    G = K.Graph.from_synth(g)
+    for direction in (0, 1, 2):
+        say("rmat14 hier", direction)
+        G.set_options(direction=direction)
+        assert_all_same(G.search_batch(qs), want, f"hier dir {direction}")
+    for i in range(0, 64, 9):
+        assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"hier plain {i}")
+    G.close()
+
+
+@pytest.fixture(scope="module")
+def rmat20(K):
+    g, qs = workloads.rmat20_q4()
+    say("rmat20 load", g.n, g.m)
+    return g, qs, oracle.Oracle(g), K.Graph.from_synth(g)
+
+
+def test_rmat20_q4_plain(K, rmat20):
+    g, qs, o, G = rmat20
+    sample = qs[:12]
+    want = oracle_results(o, sample)
+    for i, q in enumerate(sample):
+        say("rmat20 plain", i)
+        assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"rmat20 plain {i}")
+    say("rmat20 q4 batch")
+    assert_all_same(G.search_batch(sample), want, "rmat20 q4 batch")
+
+
+def test_rmat20_batch256(K, rmat20):
+    g, _, o, G = rmat20
+    qs = workloads.rmat_flat_queries(256, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=3)
+    want = oracle_results(o, qs)
+    for direction in (0, 2):
+        say("rmat20 batch256", direction)
+        G.set_options(direction=direction)
+        assert_all_same(G.search_batch(qs), want, f"rmat20 batch256 dir {direction}")
+    G.set_options()
+
+
+def test_rmat20_export_certificate(K, rmat20):
+    g, qs, o, G = rmat20
+    for t in qs[0].kw[:2]:
+        say("rmat20 export", t)
+        d = G.debug_distances(t, 3)
+        assert brute.certificate(g.row_ptr, g.col, o.keyword_set(t), d, 3) == []
+
+
+def test_errors(K, chunglu):
+    g, o, G = chunglu
+    for bad in ([10_000], [-1]):
+        with pytest.raises(K.KwsError) as e:
+            G.keyword_search(bad, 3, 10)
+        assert e.value.status == K.EINVAL
+    with pytest.raises(K.KwsError):
+        G.keyword_search([1], 16, 10)
+    with pytest.raises(K.KwsError):
+        G.keyword_search(list(range(65)), 2, 10)
+    with pytest.raises(K.KwsError):
+        G.keyword_search([1], 2, K.MAX_K + 1)
+    # 64 distinct keywords is the limit and works
+    r = G.keyword_search(list(range(64)), 1, 5)
+    w = o.search(list(range(64)), 1, 5)
+    assert_same(r, w, "64 keywords")
