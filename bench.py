@@ -1,0 +1,246 @@
+"""Benchmark of the MI355X keyword-search hot path.
+
+Default workload (the configuration the headline metric is quoted on): the
+R-MAT(.57,.19,.19,.05) graph with 2^20 vertices and 2^24 sampled edges,
+10,000 Zipf(1.0) labels with 1-3 per vertex, and a set of 100 queries of 4
+keywords each, d_max = 3, top-20. One step = one batched pass of the whole
+hot path (plan, seed, level expansion, finalize, root filter and score,
+top-k, answer graphs, result copy) over those 100 queries; inputs (graph,
+labels) are resident in HBM before timing starts.
+
+Printed as one JSON line: queries/s of the batched path (value), GTEPS,
+per-step latency percentiles, the plain one-query-per-call path on the same
+queries (qps, p50/p99 latency, speedup), the roofline of the dominant kernel
+from HIP events recorded on the library's stream during the timed steps, and
+the CPU oracle timed on a bounded sample on one host core.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "keyword queries/sec + GTEPS (% of HBM roofline) at d_max=3; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str, scale: int | None, nq: int | None):
+    from synth import workloads as W
+    if name == "rmat20_q4":
+        g, qs = W.rmat20_q4(scale or 20, nq or 100)
+        desc = dict(graph="R-MAT(.57,.19,.19,.05) 2^%d vertices, 2^%d sampled edges" % (scale or 20, (scale or 20) + 4),
+                    labels="10000 labels Zipf(1.0), 1-3 per vertex", keywords=4, d_max=3, k=20)
+    elif name == "rmat20_batch256":
+        g, qs = W.rmat20_batch256(scale or 20, nq or 256)
+        desc = dict(graph="R-MAT 2^%d vertices" % (scale or 20), keywords="2-8", d_max="2-4", k=20)
+    elif name == "chunglu10k":
+        g = W.chunglu10k()
+        qs = W.chunglu10k_queries(nq or 101)
+        desc = dict(graph="Chung-Lu 2.1, 10k vertices, 50k edges", keywords=2, d_max=3, k=10)
+    elif name == "rmat24_hier":
+        g, qs = W.rmat24_hier(scale or 24, nq or 512)
+        desc = dict(graph="R-MAT 2^%d vertices, type tree 8^6" % (scale or 24), keywords="2-6", d_max=3, k=50)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return g, qs, desc
+
+
+def byte_model(st: dict, n: int, kernel: str) -> float:
+    """Algorithmic bytes of all launches of one kernel class in one step.
+
+    expansion (push or pull) of level l, with U_l the frontier vertices,
+    E_l their in-edges and T_l the vertices that gain a lane (= U_{l+1}),
+    W the 64-lane words: 8|U_l| + 4E_l + 8W|U_l| + 16W|T_l|.
+    finalize: one streaming pass over n*Wp words reading nxt and vis and
+    writing the next frontier: 24 bytes per vertex-word and level.
+    score: 8*W*n*(1 + planes).
+    """
+    W, Wp, L = st["words"], st["words_padded"], st["levels"]
+    f, fe, pulled = st["frontier"], st["frontier_edges"], st["pulled"]
+    if kernel in ("pull", "push"):
+        want = 1 if kernel == "pull" else 0
+        tot = 0.0
+        for lv in range(L):
+            if (pulled[lv] == 1) != (want == 1) or f[lv] == 0:
+                continue
+            tot += 8 * f[lv] + 4 * fe[lv] + 8 * W * f[lv] + 16 * W * f[lv + 1]
+        return tot
+    if kernel == "finalize":
+        return 24.0 * n * Wp * (L + 1)
+    if kernel == "score":
+        planes = max(1, int(np.ceil(np.log2(L + 1)))) if L > 0 else 0
+        return 8.0 * W * n * (1 + planes)
+    return 0.0
+
+
+def cpu_baseline(g, qs, budget_s: float):
+    import oracle
+    o = oracle.Oracle(g)
+    t0 = time.perf_counter()
+    done = 0
+    for q in qs:
+        o.search(q.kw, q.d_max, q.k)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    o.close()
+    return done, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20_q4")
+    ap.add_argument("--scale", type=int, default=None)
+    ap.add_argument("--queries", type=int, default=None)
+    ap.add_argument("--tile-words", type=int, default=0)
+    ap.add_argument("--direction", type=int, default=0)
+    ap.add_argument("--alpha", type=float, default=0.0)
+    ap.add_argument("--graph", type=int, default=0, help="replay a captured hipGraph per batch shape")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--plain", type=int, default=100, help="queries timed through the plain path")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0, help="also run a plain copy of this size")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(queries would shard across GPUs with a replicated graph; not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2504_09311_amd as K
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log("generating workload", args.workload)
+    g, qs, desc = make_workload(args.workload, args.scale, args.queries)
+    log("graph", g.n, "vertices", g.m, "edges;", len(qs), "queries")
+    t0 = time.perf_counter()
+    G = K.Graph.from_synth(g)
+    load_s = time.perf_counter() - t0
+    G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words, use_graph=args.graph)
+    log("graph loaded in %.2f s" % load_s)
+
+    # ---- batched path: warmup, then K timed steps
+    for _ in range(args.warmup):
+        G.search_batch(qs)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        G.profile_enable(True)
+        G.profile_reset()
+    step_ms = []
+    te_total = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        res = G.search_batch(qs)
+        step_ms.append((time.perf_counter() - a) * 1e3)
+        te_total += sum(r.te for r in res)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    G.profile_enable(False)
+    prof = G.profile_read()
+    st = G.last_batch_stats().as_dict()
+    log("timed %d steps in %.3f s" % (args.steps, wall))
+
+    qps = len(qs) * args.steps / wall
+    gteps = te_total / wall / 1e9
+    ms_per_step = wall * 1e3 / args.steps
+
+    # ---- roofline of the dominant kernel (HIP events on the library's stream)
+    kernels = {k: dict(launches=v[0], total_ms=round(v[1], 4),
+                       avg_us=round(v[1] * 1e3 / v[0], 3) if v[0] else 0.0)
+               for k, v in prof.items() if v[0]}
+    modeled = {k: byte_model(st, g.n, k) for k in ("pull", "push", "finalize", "score")}
+    roofline = None
+    if kernels:
+        cand = [k for k in modeled if k in kernels and modeled[k] > 0]
+        if cand:
+            dom = max(cand, key=lambda k: kernels[k]["total_ms"])
+            launches = kernels[dom]["launches"]
+            per_launch_bytes = modeled[dom] * args.steps / launches
+            avg_s = kernels[dom]["total_ms"] / 1e3 / launches
+            achieved = per_launch_bytes / avg_s / 1e9
+            roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                            bytes_per_launch=int(per_launch_bytes), avg_launch_us=round(avg_s * 1e6, 3),
+                            launches=launches)
+
+    # ---- plain path: one query per call, same queries
+    plain = None
+    if args.plain > 0:
+        pq = qs[: args.plain]
+        for q in pq[:3]:
+            G.keyword_search(q.kw, q.d_max, q.k)
+        lat = []
+        t0 = time.perf_counter()
+        for q in pq:
+            a = time.perf_counter()
+            G.keyword_search(q.kw, q.d_max, q.k)
+            lat.append((time.perf_counter() - a) * 1e3)
+        pw = time.perf_counter() - t0
+        plain = dict(queries=len(pq), qps=round(len(pq) / pw, 2), p50_ms=round(float(np.percentile(lat, 50)), 4),
+                     p99_ms=round(float(np.percentile(lat, 99)), 4))
+
+    if args.copy_probe_mb:
+        x = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if args.cpu_budget > 0:
+        log("timing the CPU oracle (one thread)")
+        done, dt = cpu_baseline(g, qs, args.cpu_budget)
+        cpu = dict(value=round(done / dt, 4), unit="queries/s", cores=1, kind="oracle",
+                   sample=f"first {done} of the {len(qs)} queries of this workload, single-threaded oracle "
+                          f"({dt:.1f} s)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": dict(workload=args.workload, queries_per_step=len(qs), path="batched", n=g.n, m=g.m, **desc),
+        "gteps": round(gteps, 3),
+        "step_latency_ms": dict(p50=round(float(np.percentile(step_ms, 50)), 4),
+                                p99=round(float(np.percentile(step_ms, 99)), 4)),
+        "plain": plain,
+        "speedup_vs_plain": round(qps / plain["qps"], 2) if plain else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "batch": st,
+        "load_s": round(load_s, 3),
+    }
+    print(json.dumps(out), flush=True)
+    G.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -177,18 +177,26 @@ kws_status kws_profile_reset(kws_graph *g);
 kws_status kws_profile_read(kws_graph *g, int32_t id, int64_t *launches, double *total_ms);
 const char *kws_profile_name(int32_t id);
 
-/* Statistics of the last batch: lanes, words, per-level direction. */
+/* Statistics of the last batch (summed over its device passes).
+ * Entry l of the per-level arrays describes the frontier entering level l
+ * (l = 0 is the keyword vertices themselves; l = d_max the last vertices
+ * reached): vertices with at least one lane whose distance is exactly l,
+ * their summed in-degree, and the out-degree sum of vertices still missing a
+ * lane (the pull cost bound). pulled[l] = 1 if level l -> l+1 ran as pull. */
 typedef struct {
   int32_t queries;
   int32_t lanes;           /* distinct (keyword, d_max) lanes after sharing */
   int32_t lane_slots;      /* sum of per-query distinct keyword counts */
-  int32_t words;
+  int32_t words;           /* 64-lane mask words */
+  int32_t words_padded;    /* words rounded up to whole tiles */
   int32_t tiles;
   int32_t tile_words;
   int32_t levels;
-  int32_t pulled[KWS_MAX_DMAX];     /* 1 if level l expanded by pull */
-  int64_t frontier[KWS_MAX_DMAX];   /* frontier vertices entering level l */
-  int64_t frontier_edges[KWS_MAX_DMAX];
+  int32_t passes;
+  int32_t pulled[KWS_MAX_DMAX + 1];
+  int64_t frontier[KWS_MAX_DMAX + 1];
+  int64_t frontier_edges[KWS_MAX_DMAX + 1];
+  int64_t unfinished_edges[KWS_MAX_DMAX + 1];
 } kws_batch_stats;
 kws_status kws_last_batch_stats(kws_graph *g, kws_batch_stats *st);
 

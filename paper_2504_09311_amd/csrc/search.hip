@@ -178,7 +178,6 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, int L) {
         anyf |= fnew;
       }
     }
-    if (last) continue;
     const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
     const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
     const bool take = valid && gl == 0 && fflag;
@@ -195,7 +194,7 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, int L) {
       s_base = c ? atomicAdd((unsigned long long *)&st[0], (unsigned long long)((c << 32) | e)) : 0ull;
     }
     __syncthreads();
-    if (take) {
+    if (take && !last) {
       int32_t cpre = 0, epre = 0;
       for (int w = 0; w < wid; w++) { cpre += s_wcnt[w]; epre += s_wedge[w]; }
       const int32_t pos = (int32_t)(s_base >> 32) + cpre + wpre;
@@ -259,20 +258,9 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass P, int L, int Wq) {
 // thread (e, w) ORs word w of the frontier mask of every E-th out-neighbour.
 // Early exit once the group has found every lane the vertex still misses.
 template <int T, int S, bool SEG>
-__global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, int L, int bin) {
-  if (pick_dir(P.stats + (size_t)L * 4, P.alpha, P.force_dir) != 2) return;
+__device__ __forceinline__ void pull_rows(const Pass &P, int L, const int32_t *items, int64_t n_items, int tile,
+                                          int bb, int bpt) {
   constexpr int E = S / T, GPB = BLOCK / S, U = 4;
-  int64_t n_items;
-  const int32_t *items = nullptr;
-  if (SEG) {
-    n_items = P.n_hub;
-  } else {
-    items = P.bin_vtx + P.bin_begin[bin];
-    n_items = P.bin_begin[bin + 1] - P.bin_begin[bin];
-  }
-  const int bpt = gridDim.x / P.tiles;
-  const int tile = blockIdx.x / bpt, bb = blockIdx.x % bpt;
-  if (tile >= P.tiles) return;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -315,6 +303,33 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, int L, int bin) {
       else nxt[(size_t)v * T + w] = acc;
     }
   }
+}
+
+// One launch covers every degree bin: blocks [boff[b], boff[b+1]) serve bin b
+// (b = 3 is the hub chunks), tiles x blocks-per-tile inside each range.
+struct PullGrid { int32_t boff[BIN_COUNT + 2]; };
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, int L, const PullGrid pg) {
+  if (pick_dir(P.stats + (size_t)L * 4, P.alpha, P.force_dir) != 2) return;
+  constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
+  const int bid = blockIdx.x;
+  if (bid >= pg.boff[BIN_COUNT + 1]) return;   // the grid has one block even when every bin is empty
+  int b = 0;
+  while (b < BIN_COUNT && bid >= pg.boff[b + 1]) b++;
+  const int nblk = pg.boff[b + 1] - pg.boff[b];
+  const int bpt = nblk / P.tiles, lb = bid - pg.boff[b];
+  const int tile = lb / bpt, bb = lb % bpt;
+  if (tile >= P.tiles) return;
+  if (b == BIN_COUNT) {
+    pull_rows<T, 64, true>(P, L, nullptr, P.n_hub, tile, bb, bpt);
+    return;
+  }
+  const int32_t *items = P.bin_vtx + P.bin_begin[b];
+  const int64_t n_items = P.bin_begin[b + 1] - P.bin_begin[b];
+  if (b == BIN_SMALL) pull_rows<T, S_SMALL, false>(P, L, items, n_items, tile, bb, bpt);
+  else if (b == BIN_MEDIUM) pull_rows<T, S_MED, false>(P, L, items, n_items, tile, bb, bpt);
+  else pull_rows<T, 64, false>(P, L, items, n_items, tile, bb, bpt);
 }
 
 // ---- score: per vertex and query, root test, score histogram per chunk and
@@ -726,6 +741,18 @@ kws_status run_pass_kernels(kws_graph *g, const Pass &P, int Wq, bool capture_ok
   }
   KWS_TRY(launch_check("finalize"));
   constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
+  PullGrid pg;
+  {
+    const int sizes[BIN_COUNT + 1] = {S_SMALL, S_MED, 64, 64};
+    pg.boff[0] = 0;
+    for (int b = 0; b <= BIN_COUNT; b++) {
+      const int64_t items = b < BIN_COUNT ? P.bin_begin[b + 1] - P.bin_begin[b] : P.n_hub;
+      const int64_t gpb = BLOCK / sizes[b];
+      const int64_t bpt = items ? std::min<int64_t>((items + gpb - 1) / gpb, 16384 / P.tiles + 1) : 0;
+      pg.boff[b + 1] = pg.boff[b] + (int32_t)(bpt * P.tiles);
+    }
+  }
+  const unsigned pg_total = (unsigned)std::max(1, pg.boff[BIN_COUNT + 1]);
   for (int L = 0; L < P.D; L++) {
     {
       Timer t(prof, s, KC_PUSH);
@@ -734,17 +761,7 @@ kws_status run_pass_kernels(kws_graph *g, const Pass &P, int Wq, bool capture_ok
     KWS_TRY(launch_check("push"));
     {
       Timer t(prof, s, KC_PULL);
-      auto grid_of = [&](int64_t items, int S) {
-        const int64_t gpb = BLOCK / S;
-        const int64_t bpt = std::max<int64_t>(1, std::min<int64_t>((items + gpb - 1) / gpb, 16384 / P.tiles + 1));
-        return (unsigned)(bpt * P.tiles);
-      };
-      const int64_t nb0 = P.bin_begin[1] - P.bin_begin[0], nb1 = P.bin_begin[2] - P.bin_begin[1],
-                    nb2 = P.bin_begin[3] - P.bin_begin[2];
-      if (nb0) k_pull<T, S_SMALL, false><<<grid_of(nb0, S_SMALL), BLOCK, 0, s>>>(P, L, BIN_SMALL);
-      if (nb1) k_pull<T, S_MED, false><<<grid_of(nb1, S_MED), BLOCK, 0, s>>>(P, L, BIN_MEDIUM);
-      if (nb2) k_pull<T, 64, false><<<grid_of(nb2, 64), BLOCK, 0, s>>>(P, L, BIN_LARGE);
-      if (P.n_hub) k_pull<T, 64, true><<<grid_of(P.n_hub, 64), BLOCK, 0, s>>>(P, L, 0);
+      k_pull<T><<<pg_total, BLOCK, 0, s>>>(P, L, pg);
     }
     KWS_TRY(launch_check("pull"));
     {
@@ -1118,18 +1135,22 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   bs.lanes += n_lanes;
   bs.lane_slots += pk.lane_slots;
   bs.words += W;
+  bs.words_padded += Wp;
   bs.tiles += tiles;
   bs.tile_words = T;
   bs.levels = std::max(bs.levels, D);
-  for (int L = 0; L < D && L < KWS_MAX_DMAX; L++) {
+  bs.passes += 1;
+  for (int L = 0; L <= D && L <= KWS_MAX_DMAX; L++) {
     const uint64_t packed = h_stats[L * 4];
     const uint32_t nf = (uint32_t)(packed >> 32), mf = (uint32_t)packed;
+    bs.frontier[L] += nf;
+    bs.frontier_edges[L] += mf;
+    bs.unfinished_edges[L] += (int64_t)h_stats[L * 4 + 1];
+    if (L == D) break;
     int dir = 0;
     if (nf) dir = (o.direction == 1 || o.direction == 2) ? o.direction
                   : ((double)o.alpha * mf > (double)h_stats[L * 4 + 1] ? 2 : 1);
     bs.pulled[L] |= dir == 2;
-    bs.frontier[L] += nf;
-    bs.frontier_edges[L] += mf;
   }
   return KWS_OK;
 }

@@ -60,9 +60,19 @@ class GraphInfo(C.Structure):
 
 class BatchStats(C.Structure):
     _fields_ = [("queries", C.c_int32), ("lanes", C.c_int32), ("lane_slots", C.c_int32),
-                ("words", C.c_int32), ("tiles", C.c_int32), ("tile_words", C.c_int32),
-                ("levels", C.c_int32), ("pulled", C.c_int32 * MAX_LEVELS),
-                ("frontier", C.c_int64 * MAX_LEVELS), ("frontier_edges", C.c_int64 * MAX_LEVELS)]
+                ("words", C.c_int32), ("words_padded", C.c_int32), ("tiles", C.c_int32),
+                ("tile_words", C.c_int32), ("levels", C.c_int32), ("passes", C.c_int32),
+                ("pulled", C.c_int32 * (MAX_LEVELS + 1)), ("frontier", C.c_int64 * (MAX_LEVELS + 1)),
+                ("frontier_edges", C.c_int64 * (MAX_LEVELS + 1)),
+                ("unfinished_edges", C.c_int64 * (MAX_LEVELS + 1))]
+
+    def as_dict(self):
+        L = self.levels
+        return dict(queries=self.queries, lanes=self.lanes, lane_slots=self.lane_slots, words=self.words,
+                    words_padded=self.words_padded, tiles=self.tiles, tile_words=self.tile_words,
+                    levels=L, passes=self.passes, pulled=list(self.pulled[:L]),
+                    frontier=list(self.frontier[:L + 1]), frontier_edges=list(self.frontier_edges[:L + 1]),
+                    unfinished_edges=list(self.unfinished_edges[:L + 1]))
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
