@@ -138,7 +138,7 @@ def main():
 
     # ---- batched path: warmup, then K timed steps
     for _ in range(args.warmup):
-        G.search_batch(qs)
+        G.search_batch_flat(qs)
     torch.cuda.synchronize()
     if not args.no_profile:
         G.profile_enable(True)
@@ -149,9 +149,9 @@ def main():
     t_start = time.perf_counter()
     for i in range(args.steps):
         a = time.perf_counter()
-        res = G.search_batch(qs)
+        res = G.search_batch_flat(qs)
         step_ms.append((time.perf_counter() - a) * 1e3)
-        te_total += sum(r.te for r in res)
+        te_total += int(res["te"].sum())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     G.profile_enable(False)

@@ -127,6 +127,33 @@ kws_status kws_search_batch(kws_graph *g, const kws_query *qs, int32_t nq, kws_r
 
 void kws_result_free(kws_result *r);
 
+/* Batched path with flat output: the same answers as kws_search_batch,
+ * returned as one set of arrays for the whole batch (allocated by the
+ * library; release with kws_batch_result_free).
+ *  root_ptr[nq+1]   roots/scores of query q: [root_ptr[q], root_ptr[q+1])
+ *  kw_ptr[nq+1]     distinct keywords of query q in kw[]
+ *  dist_ptr[nq+1]   kw_dist entries of query q (row-major n_roots x n_kw)
+ *  edge_ptr[total_roots+1]  answer edges of the r-th root of the batch
+ *                   (roots numbered in root_ptr order)
+ *  te[nq]           per-query scanned-edge counts (see kws_result.te) */
+typedef struct {
+  int32_t nq;
+  int64_t total_roots;
+  int64_t *root_ptr;
+  int32_t *roots;
+  int32_t *scores;
+  int64_t *kw_ptr;
+  int32_t *kw;
+  int64_t *dist_ptr;
+  uint8_t *kw_dist;
+  int64_t *edge_ptr;
+  int32_t *edge_src;
+  int32_t *edge_dst;
+  int64_t *te;
+} kws_batch_result;
+kws_status kws_search_batch_flat(kws_graph *g, const kws_query *qs, int32_t nq, kws_batch_result *out);
+void kws_batch_result_free(kws_batch_result *r);
+
 /* Verification: dist_n[n] = truncated distance of every vertex to keyword
  * kw (KWS_DIST_INF beyond d_max), computed by the same device kernels. */
 kws_status kws_debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist_n);

@@ -188,6 +188,13 @@ void Profiler::release() {
 
 }  // namespace kws
 
+template <class T>
+static T *copy_out(const std::vector<T> &v) {
+  T *p = (T *)malloc(sizeof(T) * std::max<size_t>(1, v.size()));
+  if (p && !v.empty()) memcpy(p, v.data(), sizeof(T) * v.size());
+  return p;
+}
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -238,6 +245,44 @@ kws_status kws_search_batch(kws_graph *g, const kws_query *qs, int32_t nq, kws_r
   if (!g) return kws::fail(KWS_EINVAL, "null graph");
   std::lock_guard<std::mutex> lk(g->mu);
   return kws::search(g, qs, nq, out);
+}
+
+kws_status kws_search_batch_flat(kws_graph *g, const kws_query *qs, int32_t nq, kws_batch_result *out) {
+  kws::clear_error();
+  if (!g || !out) return kws::fail(KWS_EINVAL, "null argument");
+  memset(out, 0, sizeof(*out));
+  kws::FlatOut f;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    kws_status st = kws::search(g, qs, nq, nullptr, &f);
+    if (st != KWS_OK) return st;
+  }
+  out->nq = nq;
+  out->total_roots = (int64_t)f.roots.size();
+  out->root_ptr = copy_out(f.root_ptr);
+  out->roots = copy_out(f.roots);
+  out->scores = copy_out(f.scores);
+  out->kw_ptr = copy_out(f.kw_ptr);
+  out->kw = copy_out(f.kw);
+  out->dist_ptr = copy_out(f.dist_ptr);
+  out->kw_dist = copy_out(f.kw_dist);
+  out->edge_ptr = copy_out(f.edge_ptr);
+  out->edge_src = copy_out(f.edge_src);
+  out->edge_dst = copy_out(f.edge_dst);
+  out->te = copy_out(f.te);
+  if (!out->root_ptr || !out->roots || !out->scores || !out->kw_ptr || !out->kw || !out->dist_ptr ||
+      !out->kw_dist || !out->edge_ptr || !out->edge_src || !out->edge_dst || !out->te) {
+    kws_batch_result_free(out);
+    return kws::fail(KWS_ENOMEM, "host result allocation");
+  }
+  return KWS_OK;
+}
+
+void kws_batch_result_free(kws_batch_result *r) {
+  if (!r) return;
+  free(r->root_ptr); free(r->roots); free(r->scores); free(r->kw_ptr); free(r->kw); free(r->dist_ptr);
+  free(r->kw_dist); free(r->edge_ptr); free(r->edge_src); free(r->edge_dst); free(r->te);
+  memset(r, 0, sizeof(*r));
 }
 
 void kws_result_free(kws_result *r) {

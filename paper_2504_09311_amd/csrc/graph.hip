@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "kws_internal.h"
 
@@ -226,6 +227,27 @@ kws_status type_preorder(const int32_t *parent, int32_t nt, std::vector<int32_t>
   return KWS_OK;
 }
 
+// Rows of the forward CSR sorted by neighbour id (the answer walk stops at
+// the first qualifying neighbour). Returns an empty vector when the input is
+// already sorted.
+std::vector<int32_t> sorted_rows(const int32_t *row_ptr, const int32_t *col, int32_t n, int64_t m) {
+  bool sorted = true;
+  for (int32_t u = 0; u < n && sorted; u++)
+    for (int32_t e = row_ptr[u] + 1; e < row_ptr[u + 1]; e++)
+      if (col[e - 1] > col[e]) { sorted = false; break; }
+  std::vector<int32_t> out;
+  if (sorted) return out;
+  out.assign(col, col + m);
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; t++)
+    th.emplace_back([&, t] {
+      for (int32_t u = t; u < n; u += nt) std::sort(out.begin() + row_ptr[u], out.begin() + row_ptr[u + 1]);
+    });
+  for (auto &x : th) x.join();
+  return out;
+}
+
 }  // namespace
 
 kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
@@ -256,9 +278,12 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
 #define STEP(x) do { st = (x); if (st != KWS_OK) return bail(st); } while (0)
 #define HSTEP(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return bail(fail(KWS_EDEVICE, "%s: %s", #x, hipGetErrorString(e_))); } while (0)
 
-  // forward CSR
+  // forward CSR, rows sorted by neighbour id
   STEP(upload(&g->fwd_ptr, d->row_ptr, (size_t)n + 1, &bytes, "row_ptr"));
-  STEP(upload(&g->fwd_col, d->col, (size_t)m, &bytes, "col"));
+  {
+    std::vector<int32_t> sc = sorted_rows(d->row_ptr, d->col, n, m);
+    STEP(upload(&g->fwd_col, sc.empty() ? d->col : sc.data(), (size_t)m, &bytes, "col"));
+  }
   // reverse CSR: in-degree count, scan, scatter
   int32_t *cnt = nullptr, *cursor = nullptr;
   int64_t scratch = 0;

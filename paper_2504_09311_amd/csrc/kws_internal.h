@@ -144,9 +144,16 @@ struct kws_graph {
 };
 
 namespace kws {
+// Growing flat output of a batch (turned into a kws_batch_result at the end).
+struct FlatOut {
+  std::vector<int64_t> root_ptr{0}, kw_ptr{0}, dist_ptr{0}, edge_ptr{0};
+  std::vector<int32_t> roots, scores, kw, edge_src, edge_dst;
+  std::vector<uint8_t> kw_dist;
+  std::vector<int64_t> te;
+};
 kws_status load_graph(const kws_graph_desc *d, kws_graph **out);
 void free_graph(kws_graph *g);
 void default_options(kws_options *o);
-kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out);
+kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out, FlatOut *flat = nullptr);
 kws_status debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist);
 }  // namespace kws

@@ -35,7 +35,7 @@ struct Pass {
   int32_t chunks, CH, nhist, hist_lds, te_lds;
   int32_t force_dir;
   float alpha;
-  int64_t total_seeds, n_hub, total_slots;
+  int64_t total_seeds, n_hub, total_slots, total_kd;
   int64_t bin_begin[BIN_COUNT + 1];
   size_t pstride;              // words per plane = tiles * n * T
   // graph
@@ -54,6 +54,7 @@ struct Pass {
   const int32_t *q_word, *q_dmax, *q_nk, *q_kcap, *q_hoff, *q_coff, *q_ccap, *q_roff, *q_kdoff,
       *q_eoff, *q_ecap, *q_boff;
   const uint8_t *bits;               // lane bit of each query keyword, keyword order
+  const int32_t *q_lane;             // lane id of each query keyword, keyword order
   // zeroed per pass
   uint64_t *zero0; int64_t zero0_words;
   uint64_t *zero1; int64_t zero1_words;
@@ -129,77 +130,107 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
 
 // ---- finalize level L -> L+1 (L = -1 turns the seeds into level 0)
 // new = nxt & ~vis & act[L+1]; vis |= new; distance planes; next frontier
-// buffer; nxt cleared; frontier list compaction with in-edge offsets; the
-// statistics that pick the direction of the next level.
+// buffer; nxt cleared; the statistics that pick the direction of the next
+// level. Frontier vertices are compacted into LDS per chunk of FIN_CHUNK
+// vertices (wavefront ballot + prefix sums), then one atomic per chunk
+// reserves their place in the global list and its in-edge offsets.
+constexpr int FIN_CHUNK = 512;
+
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, int L) {
-  extern __shared__ uint64_t s_live[];
+  extern __shared__ uint64_t s_live[];                    // [Wp]
+  __shared__ int32_t s_lv[FIN_CHUNK], s_le[FIN_CHUNK];
   __shared__ int32_t s_wcnt[BLOCK / 64], s_wedge[BLOCK / 64];
+  __shared__ int32_t s_cnt, s_edges;
   __shared__ uint64_t s_base;
   const bool first = L < 0;
   const bool last = L + 1 >= P.D;
-  const int G = P.G, VPB = BLOCK / G;
+  constexpr int G = T, VPB = BLOCK / T;   // T threads per vertex, one per word of a tile
   const int tid = threadIdx.x, gl = tid & (G - 1), lane = tid & 63, wid = tid >> 6;
   const uint64_t gmask = group_bits(lane, G);
   const uint64_t *act_new = P.act + (size_t)(L + 1) * P.Wp;
   const uint64_t *act_nn = P.act + (size_t)(L + 2) * P.Wp;
   uint64_t *fr_next = ((L + 1) & 1) ? P.fr1 : P.fr0;
   uint64_t *st = P.stats + (size_t)(L + 1) * 4;
-  if (!last) {
-    for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
-    __syncthreads();
-  }
+  for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
   uint64_t mu_acc = 0;
-  for (int64_t vb = (int64_t)blockIdx.x * VPB; vb < P.n; vb += (int64_t)gridDim.x * VPB) {
-    const int64_t v = vb + tid / G;
-    const bool valid = v < P.n;
-    uint64_t anyf = 0, anyneed = 0;
-    if (valid) {
-      for (int j = gl; j < P.Wp; j += G) {
-        const size_t idx = ((size_t)(j / T) * P.n + v) * T + (j % T);
-        const uint64_t nx = P.nxt[idx];
-        const uint64_t old = first ? 0ull : P.vis[idx];
-        const uint64_t fnew = nx & ~old & act_new[j];
-        const uint64_t nv = old | fnew;
-        if (first) {
-          P.vis[idx] = nv;
-          for (int b = 0; b < P.B; b++) P.planes[b * P.pstride + idx] = 0;
-        } else if (fnew) {
-          P.vis[idx] = nv;
-          for (int b = 0; b < P.B; b++)
-            if (((L + 1) >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
+  const int64_t nchunks = ((int64_t)P.n + FIN_CHUNK - 1) / FIN_CHUNK;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (tid == 0) { s_cnt = 0; s_edges = 0; }
+    __syncthreads();
+    const int64_t c0 = c * FIN_CHUNK, c1 = min((int64_t)P.n, c0 + FIN_CHUNK);
+    for (int64_t vb = c0; vb < c1; vb += VPB) {
+      const int64_t v = vb + tid / G;
+      const bool valid = v < c1;
+      uint64_t anyf = 0, anyneed = 0;
+      if (valid) {
+        constexpr int TG = 8;   // tiles whose words are loaded before any store
+        for (int t0 = 0; t0 < P.tiles; t0 += TG) {
+          uint64_t nxv[TG], oldv[TG];
+#pragma unroll
+          for (int k = 0; k < TG; k++) {
+            const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
+            nxv[k] = t0 + k < P.tiles ? P.nxt[idx] : 0ull;
+            oldv[k] = (t0 + k < P.tiles && !first) ? P.vis[idx] : 0ull;
+          }
+#pragma unroll
+          for (int k = 0; k < TG; k++) {
+            if (t0 + k >= P.tiles) break;
+            const int j = (t0 + k) * T + gl;
+            const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
+            const uint64_t nx = nxv[k], old = oldv[k];
+            const uint64_t fnew = nx & ~old & act_new[j];
+            const uint64_t nv = old | fnew;
+            if (first) {
+              P.vis[idx] = nv;
+              for (int b = 0; b < P.B; b++) P.planes[b * P.pstride + idx] = 0;
+            } else if (fnew) {
+              P.vis[idx] = nv;
+              for (int b = 0; b < P.B; b++)
+                if (((L + 1) >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
+            }
+            if (!last) {
+              fr_next[idx] = fnew;
+              if (fnew) atomicOr((unsigned long long *)&s_live[j], fnew);
+              anyneed |= act_nn[j] & ~nv;
+            }
+            if (nx) P.nxt[idx] = 0;
+            anyf |= fnew;
+          }
         }
-        if (!last) {
-          fr_next[idx] = fnew;
-          if (fnew) atomicOr((unsigned long long *)&s_live[j], fnew);
-          anyneed |= act_nn[j] & ~nv;
-        }
-        if (nx) P.nxt[idx] = 0;
-        anyf |= fnew;
       }
+      const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
+      const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
+      const bool take = valid && gl == 0 && fflag;
+      if (valid && gl == 0 && nflag) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
+      const int32_t indeg = take ? P.rev_ptr[v + 1] - P.rev_ptr[v] : 0;
+      const uint64_t bal = __ballot(take);
+      const int32_t wpre = __popcll(bal & ((1ull << lane) - 1ull));
+      const int32_t eincl = wave_incl_scan(indeg, lane);
+      if (lane == 63) { s_wcnt[wid] = __popcll(bal); s_wedge[wid] = eincl; }
+      __syncthreads();
+      if (take) {
+        int32_t cpre = s_cnt, epre = s_edges;
+        for (int w = 0; w < wid; w++) { cpre += s_wcnt[w]; epre += s_wedge[w]; }
+        s_lv[cpre + wpre] = (int32_t)v;
+        s_le[cpre + wpre] = epre + eincl - indeg;
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int w = 0; w < BLOCK / 64; w++) { s_cnt += s_wcnt[w]; s_edges += s_wedge[w]; }
+      __syncthreads();
     }
-    const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
-    const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
-    const bool take = valid && gl == 0 && fflag;
-    if (valid && gl == 0 && nflag) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
-    const int32_t indeg = take ? P.rev_ptr[v + 1] - P.rev_ptr[v] : 0;
-    const uint64_t bal = __ballot(take);
-    const int32_t wpre = __popcll(bal & ((1ull << lane) - 1ull));
-    const int32_t eincl = wave_incl_scan(indeg, lane);
-    if (lane == 63) { s_wcnt[wid] = __popcll(bal); s_wedge[wid] = eincl; }
+    if (tid == 0)
+      s_base = s_cnt ? atomicAdd((unsigned long long *)&st[0],
+                                 (unsigned long long)(((uint64_t)s_cnt << 32) | (uint32_t)s_edges))
+                     : 0ull;
     __syncthreads();
-    if (tid == 0) {
-      uint64_t c = 0, e = 0;
-      for (int w = 0; w < BLOCK / 64; w++) { c += (uint64_t)s_wcnt[w]; e += (uint64_t)s_wedge[w]; }
-      s_base = c ? atomicAdd((unsigned long long *)&st[0], (unsigned long long)((c << 32) | e)) : 0ull;
-    }
-    __syncthreads();
-    if (take && !last) {
-      int32_t cpre = 0, epre = 0;
-      for (int w = 0; w < wid; w++) { cpre += s_wcnt[w]; epre += s_wedge[w]; }
-      const int32_t pos = (int32_t)(s_base >> 32) + cpre + wpre;
-      P.flist[pos] = (int32_t)v;
-      P.flist_eoff[pos] = (int32_t)(uint32_t)s_base + epre + eincl - indeg;
+    if (!last) {
+      const int32_t bc = (int32_t)(s_base >> 32), be = (int32_t)(uint32_t)s_base;
+      for (int i = tid; i < s_cnt; i += BLOCK) {
+        P.flist[bc + i] = s_lv[i];
+        P.flist_eoff[bc + i] = be + s_le[i];
+      }
     }
     __syncthreads();
   }
@@ -334,59 +365,86 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, int L, const PullG
 
 // ---- score: per vertex and query, root test, score histogram per chunk and
 // the scanned-edge count te (in-degree of every vertex each lane expanded).
+// Each thread holds SC_R vertices; a wavefront walks the words and their
+// queries in lockstep, so histogram updates are aggregated per distinct
+// score value and te is reduced across the wavefront once per query.
+constexpr int SC_R = 2;
+
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;
   int32_t *s_hist = (int32_t *)(s_dyn + (P.te_lds ? P.nq : 0));
-  const int G = P.G, VPB = BLOCK / G;
-  const int tid = threadIdx.x, gl = tid & (G - 1);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int split = (P.CH + BLOCK * SC_R - 1) / (BLOCK * SC_R);
   if (P.te_lds)
     for (int i = tid; i < P.nq; i += BLOCK) s_te[i] = 0;
-  for (int c = blockIdx.x; c < P.chunks; c += gridDim.x) {
+  for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
+    const int c = (int)(bid / split), part = (int)(bid % split);
     if (P.hist_lds)
       for (int i = tid; i < P.nhist; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
-    const int64_t v0 = (int64_t)c * P.CH, v1 = min((int64_t)P.n, v0 + P.CH);
-    for (int64_t vb = v0; vb < v1; vb += VPB) {
-      const int64_t v = vb + tid / G;
-      if (v >= v1) continue;
-      int32_t indeg = -1;
-      for (int j = gl; j < P.Wp; j += G) {
-        const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
-        if (qb == qe) continue;
-        const size_t idx = ((size_t)(j / T) * P.n + v) * T + (j % T);
-        const uint64_t vis = P.vis[idx];
-        if (!vis) continue;
-        uint64_t pl[4] = {0, 0, 0, 0};
-        for (int b = 0; b < P.B; b++) pl[b] = P.planes[b * P.pstride + idx];
-        if (indeg < 0) indeg = P.rev_ptr[v + 1] - P.rev_ptr[v];
-        for (int qi = qb; qi < qe; qi++) {
-          const int q = P.word_q[qi];
-          const uint64_t m = P.q_mask[q], x = vis & m;
-          if (!x) continue;
-          const int dq = P.q_dmax[q];
+    int32_t *hist = P.hist_lds ? s_hist : P.hist + (size_t)c * P.nhist;
+    const int64_t cend = min((int64_t)P.n, (int64_t)(c + 1) * P.CH);
+    const int64_t v0 = (int64_t)c * P.CH + (int64_t)part * BLOCK * SC_R;
+    int64_t vv[SC_R];
+    uint64_t indeg[SC_R];
+#pragma unroll
+    for (int r = 0; r < SC_R; r++) {
+      vv[r] = v0 + r * BLOCK + tid;
+      indeg[r] = vv[r] < cend ? (uint64_t)(P.rev_ptr[vv[r] + 1] - P.rev_ptr[vv[r]]) : 0ull;
+    }
+    for (int j = 0; j < P.Wp; j++) {
+      const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
+      if (qb == qe) continue;
+      const size_t base = (size_t)(j / T) * P.n * T + (j % T);
+      uint64_t vis[SC_R], pl[SC_R][4];
+      bool any = false;
+#pragma unroll
+      for (int r = 0; r < SC_R; r++) {
+        vis[r] = vv[r] < cend ? P.vis[base + (size_t)vv[r] * T] : 0ull;
+        for (int b = 0; b < 4; b++)
+          pl[r][b] = (b < P.B && vis[r]) ? P.planes[b * P.pstride + base + (size_t)vv[r] * T] : 0ull;
+        any |= vis[r] != 0;
+      }
+      if (__ballot(any) == 0) continue;
+      for (int qi = qb; qi < qe; qi++) {
+        const int q = P.word_q[qi];
+        const uint64_t m = P.q_mask[q];
+        const int dq = P.q_dmax[q], hq = P.q_hoff[q];
+        uint64_t t = 0;
+#pragma unroll
+        for (int r = 0; r < SC_R; r++) {
+          const uint64_t x = vis[r] & m;
           uint64_t eq = x;
-          for (int b = 0; b < P.B; b++) eq &= ((dq >> b) & 1) ? pl[b] : ~pl[b];
-          const uint64_t cnt = (uint64_t)(__popcll(x) - __popcll(eq));
-          if (cnt && indeg) {
-            const unsigned long long add = cnt * (uint64_t)indeg;
-            if (P.te_lds) atomicAdd((unsigned long long *)&s_te[q], add);
-            else atomicAdd((unsigned long long *)&P.te[q], add);
+          for (int b = 0; b < P.B; b++) eq &= ((dq >> b) & 1) ? pl[r][b] : ~pl[r][b];
+          t += (uint64_t)(__popcll(x) - __popcll(eq)) * indeg[r];
+          const bool root = x == m;
+          int sc = 0;
+          if (root)
+            for (int b = 0; b < P.B; b++) sc += __popcll(pl[r][b] & m) << b;
+          uint64_t pend = __ballot(root);
+          while (pend) {
+            const int leader = __ffsll((long long)pend) - 1;
+            const int sv = __shfl(sc, leader);
+            const uint64_t same = __ballot(root && sc == sv);
+            if (lane == leader) atomicAdd(&hist[hq + sv], (int)__popcll(same));
+            pend &= ~same;
           }
-          if (x == m) {
-            int s = 0;
-            for (int b = 0; b < P.B; b++) s += __popcll(pl[b] & m) << b;
-            const int h = P.q_hoff[q] + s;
-            if (P.hist_lds) atomicAdd(&s_hist[h], 1);
-            else atomicAdd(&P.hist[(size_t)c * P.nhist + h], 1);
+        }
+        if (__ballot(t != 0)) {
+          for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+          if (lane == 0) {
+            if (P.te_lds) atomicAdd((unsigned long long *)&s_te[q], (unsigned long long)t);
+            else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
           }
         }
       }
     }
     __syncthreads();
     if (P.hist_lds)
-      for (int i = tid; i < P.nhist; i += BLOCK) P.hist[(size_t)c * P.nhist + i] = s_hist[i];
+      for (int i = tid; i < P.nhist; i += BLOCK)
+        if (s_hist[i]) atomicAdd(&P.hist[(size_t)c * P.nhist + i], s_hist[i]);
     __syncthreads();
   }
   if (P.te_lds) {
@@ -543,17 +601,95 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const Pass P) {
   }
 }
 
-// ---- answer: one wave per (query, root). For every keyword, walk from the
-// root to the smallest-id out-neighbour one hop closer; lane 0 collects,
-// sorts and deduplicates the edges.
+// ---- answer: one wave per (query, root, keyword) walks from the root to
+// the smallest-id out-neighbour one hop closer, writing the path into the
+// keyword's segment of the root's edge slot; then one wave per (query, root)
+// merges the segments: sort, drop repeats.
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
+  constexpr int WAVES = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t waves = (int64_t)gridDim.x * WAVES;
+  for (int64_t item = (int64_t)blockIdx.x * WAVES + wid; item < P.total_kd; item += waves) {
+    int lo = 0, hi = P.nq;                      // query owning this (root, keyword) item
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (P.q_kdoff[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int q = lo, nk = P.q_nk[q];
+    const int rel = (int)(item - P.q_kdoff[q]), i = rel / nk, j = rel % nk;
+    if (i >= P.qsel[q * 4 + 0]) continue;
+    const int32_t r = P.r_roots[P.q_roff[q] + i];
+    int d = P.r_kwdist[item];
+    const int word = P.q_word[q], w = word % T, bit = P.bits[P.q_boff[q] + j];
+    const size_t tb = (size_t)(word / T) * P.n * T;
+    int2 *out = P.r_edges + P.q_eoff[q] + (size_t)i * P.q_ecap[q] + (size_t)j * P.q_dmax[q];
+    int32_t x = r;
+    int h = 0;
+    const int lid = P.q_lane[P.q_boff[q] + j];
+    while (d > 0) {
+      int32_t best = 0x7fffffff;
+      const int32_t e0 = P.fwd_ptr[x], e1 = P.fwd_ptr[x + 1];
+      const int64_t ns = P.lane_seed_off[lid + 1] - P.lane_seed_off[lid];
+      if (d == 1 && ns * 4 < (int64_t)(e1 - e0)) {
+        // last hop: the keyword's vertices are few compared with the row, so
+        // look each of them up in the sorted row and keep the smallest hit
+        const int32_t *seeds = P.inv_vtx + P.lane_seed_begin[lid];
+        int32_t mine = 0x7fffffff;
+        for (int64_t k = lane; k < ns; k += 64) {
+          const int32_t v = seeds[k];
+          int32_t lo = e0, hi = e1;
+          while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (P.fwd_col[mid] < v) lo = mid + 1; else hi = mid;
+          }
+          if (lo < e1 && P.fwd_col[lo] == v) mine = min(mine, v);
+        }
+        for (int off = 32; off > 0; off >>= 1) mine = min(mine, __shfl_xor(mine, off));
+        best = mine;
+      } else {
+        // rows are sorted by neighbour id, so the first qualifying neighbour
+        // in row order is the smallest-id one; four chunks of 64 per round
+        constexpr int U = 4;
+        for (int32_t eb = e0; eb < e1 && best == 0x7fffffff; eb += 64 * U) {
+          int32_t y[U];
+          bool ok[U];
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            const int32_t e = eb + u * 64 + lane;
+            y[u] = e < e1 ? P.fwd_col[e] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < U; u++)
+            ok[u] = y[u] >= 0 && ((P.vis[tb + (size_t)y[u] * T + w] >> bit) & 1ull);
+#pragma unroll
+          for (int u = 0; u < U; u++)
+            if (ok[u]) ok[u] = lane_dist(P, tb + (size_t)y[u] * T + w, bit) == d - 1;
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            const uint64_t bal = __ballot(ok[u]);
+            if (bal && best == 0x7fffffff) best = __shfl(y[u], __ffsll((long long)bal) - 1);
+          }
+        }
+      }
+      if (best == 0x7fffffff || h >= P.q_dmax[q]) break;   // cannot happen for a BFS-consistent state
+      if (lane == 0) out[h] = make_int2(x, best);
+      h++;
+      x = best;
+      d--;
+    }
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_answer_merge(const Pass P) {
   constexpr int WAVES = BLOCK / 64, ECAP = KWS_MAX_KW * KWS_MAX_DMAX;
   __shared__ uint64_t s_e[WAVES][ECAP];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint64_t *eb = s_e[wid];
   const int64_t waves = (int64_t)gridDim.x * WAVES;
   for (int64_t slot = (int64_t)blockIdx.x * WAVES + wid; slot < P.total_slots; slot += waves) {
+    if (lane != 0) continue;
     int lo = 0, hi = P.nq;                      // query owning this slot
     while (hi - lo > 1) {
       int mid = (lo + hi) >> 1;
@@ -561,46 +697,27 @@ __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
     }
     const int q = lo, i = (int)(slot - P.q_roff[q]);
     if (i >= P.qsel[q * 4 + 0]) continue;
-    const int32_t r = P.r_roots[P.q_roff[q] + i];
-    const int word = P.q_word[q], w = word % T, nk = P.q_nk[q], boff = P.q_boff[q];
-    const size_t tb = (size_t)(word / T) * P.n * T;
+    const int nk = P.q_nk[q], dm = P.q_dmax[q];
+    int2 *seg = P.r_edges + P.q_eoff[q] + (size_t)i * P.q_ecap[q];
+    const uint8_t *kd = P.r_kwdist + P.q_kdoff[q] + (size_t)i * nk;
     int ne = 0;
-    for (int j = 0; j < nk; j++) {
-      const int bit = P.bits[boff + j];
-      int32_t x = r;
-      int d = lane_dist(P, tb + (size_t)x * T + w, bit);
-      while (d > 0) {
-        int32_t best = 0x7fffffff;
-        for (int32_t e = P.fwd_ptr[x] + lane; e < P.fwd_ptr[x + 1]; e += 64) {
-          const int32_t y = P.fwd_col[e];
-          if (y < best) {
-            const size_t iy = tb + (size_t)y * T + w;
-            if (((P.vis[iy] >> bit) & 1ull) && lane_dist(P, iy, bit) == d - 1) best = y;
-          }
-        }
-        for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
-        if (best == 0x7fffffff || ne >= ECAP) break;   // cannot happen for a BFS-consistent state
-        if (lane == 0) eb[ne] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)best;
-        ne++;
-        x = best;
-        d--;
+    for (int j = 0; j < nk; j++)
+      for (int h = 0; h < kd[j] && h < dm; h++) {
+        const int2 e = seg[j * dm + h];
+        eb[ne++] = ((uint64_t)(uint32_t)e.x << 32) | (uint32_t)e.y;
       }
+    for (int a = 1; a < ne; a++) {             // insertion sort, then drop repeats
+      const uint64_t key = eb[a];
+      int b = a - 1;
+      while (b >= 0 && eb[b] > key) { eb[b + 1] = eb[b]; b--; }
+      eb[b + 1] = key;
     }
-    if (lane == 0) {
-      for (int a = 1; a < ne; a++) {             // insertion sort, then drop repeats
-        const uint64_t key = eb[a];
-        int b = a - 1;
-        while (b >= 0 && eb[b] > key) { eb[b + 1] = eb[b]; b--; }
-        eb[b + 1] = key;
-      }
-      int u = 0;
-      int2 *out = P.r_edges + P.q_eoff[q] + (size_t)i * P.q_ecap[q];
-      for (int a = 0; a < ne; a++) {
-        if (a > 0 && eb[a] == eb[a - 1]) continue;
-        out[u++] = make_int2((int32_t)(eb[a] >> 32), (int32_t)(uint32_t)eb[a]);
-      }
-      P.r_ecount[P.q_roff[q] + i] = u;
+    int u = 0;
+    for (int a = 0; a < ne; a++) {
+      if (a > 0 && eb[a] == eb[a - 1]) continue;
+      seg[u++] = make_int2((int32_t)(eb[a] >> 32), (int32_t)(uint32_t)eb[a]);
     }
+    P.r_ecount[slot] = u;
   }
 }
 
@@ -636,6 +753,7 @@ struct Packing {
   std::vector<int32_t> word_used;
   std::vector<int32_t> q_word;
   std::vector<std::array<uint8_t, KWS_MAX_KW>> q_bits;
+  std::vector<std::array<int32_t, KWS_MAX_KW>> q_lanes;
   std::vector<uint64_t> q_mask;
   int32_t lane_slots = 0;
 };
@@ -646,7 +764,7 @@ struct Packing {
 // on ties); otherwise a new word is opened.
 void pack(const std::vector<QIn> &qs, int qa, int qb, bool share, Packing &pk) {
   pk = Packing();
-  std::unordered_map<uint64_t, std::vector<std::pair<int32_t, int32_t>>> where;   // (kw,d) -> (word, bit)
+  std::unordered_map<uint64_t, std::vector<std::array<int32_t, 3>>> where;   // (kw,d) -> (word, bit, lane)
   std::vector<int32_t> shared_cnt;
   for (int q = qa; q < qb; q++) {
     const QIn &Q = qs[q];
@@ -656,7 +774,7 @@ void pack(const std::vector<QIn> &qs, int qa, int qb, bool share, Packing &pk) {
       for (int j = 0; j < Q.nk; j++) {
         auto it = where.find(((uint64_t)(uint32_t)Q.kw[j] << 8) | (uint64_t)Q.dmax);
         if (it != where.end())
-          for (auto &wb : it->second) shared_cnt[wb.first]++;
+          for (auto &wb : it->second) shared_cnt[wb[0]]++;
       }
       for (size_t w = 0; w < pk.word_used.size(); w++) {
         const int need = Q.nk - shared_cnt[w];
@@ -671,26 +789,30 @@ void pack(const std::vector<QIn> &qs, int qa, int qb, bool share, Packing &pk) {
       pk.word_used.push_back(0);
     }
     std::array<uint8_t, KWS_MAX_KW> bits{};
+    std::array<int32_t, KWS_MAX_KW> lids{};
     uint64_t mask = 0;
     for (int j = 0; j < Q.nk; j++) {
       const uint64_t key = ((uint64_t)(uint32_t)Q.kw[j] << 8) | (uint64_t)Q.dmax;
-      int bit = -1;
+      int bit = -1, lid = -1;
       if (share) {
         auto it = where.find(key);
         if (it != where.end())
           for (auto &wb : it->second)
-            if (wb.first == best) { bit = wb.second; break; }
+            if (wb[0] == best) { bit = wb[1]; lid = wb[2]; break; }
       }
       if (bit < 0) {
         bit = pk.word_used[best]++;
+        lid = (int)pk.lanes.size();
         pk.lanes.push_back({Q.kw[j], Q.dmax, best, bit});
-        where[key].push_back({best, bit});
+        where[key].push_back({best, bit, lid});
       }
       bits[j] = (uint8_t)bit;
+      lids[j] = lid;
       mask |= 1ull << bit;
     }
     pk.q_word.push_back(best);
     pk.q_bits.push_back(bits);
+    pk.q_lanes.push_back(lids);
     pk.q_mask.push_back(mask);
     pk.lane_slots += Q.nk;
   }
@@ -732,8 +854,7 @@ kws_status run_pass_kernels(kws_graph *g, const Pass &P, int Wq, bool capture_ok
     k_seed<T><<<clamp_grid((seed_items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P);
   }
   KWS_TRY(launch_check("seed"));
-  const int VPB = BLOCK / P.G;
-  const unsigned fin_grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + VPB - 1) / VPB, 8192));
+  const unsigned fin_grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + FIN_CHUNK - 1) / FIN_CHUNK, 8192));
   const size_t fin_lds = sizeof(uint64_t) * (size_t)P.Wp;
   {
     Timer t(prof, s, KC_FINALIZE);
@@ -773,7 +894,8 @@ kws_status run_pass_kernels(kws_graph *g, const Pass &P, int Wq, bool capture_ok
   {
     Timer t(prof, s, KC_SCORE);
     const size_t lds = (P.te_lds ? sizeof(uint64_t) * P.nq : 0) + (P.hist_lds ? sizeof(int32_t) * P.nhist : 0);
-    k_score<T><<<(unsigned)P.chunks, BLOCK, lds, s>>>(P);
+    const int64_t split = (P.CH + BLOCK * SC_R - 1) / (BLOCK * SC_R);
+    k_score<T><<<clamp_grid(P.chunks * split), BLOCK, lds, s>>>(P);
   }
   KWS_TRY(launch_check("score"));
   {
@@ -794,7 +916,8 @@ kws_status run_pass_kernels(kws_graph *g, const Pass &P, int Wq, bool capture_ok
   {
     Timer t(prof, s, KC_ANSWER);
     const int64_t waves = BLOCK / 64;
-    k_answer<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
+    k_answer<T><<<clamp_grid((P.total_kd + waves - 1) / waves), BLOCK, 0, s>>>(P);
+    k_answer_merge<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
   }
   KWS_TRY(launch_check("answer"));
   (void)capture_ok;
@@ -873,7 +996,7 @@ struct PassOut {
 constexpr kws_status PASS_TOO_WIDE = (kws_status)1;   // internal: retry with fewer queries
 
 kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, int max_words, bool export_only,
-                    uint8_t *export_dist, kws_result *out) {
+                    uint8_t *export_dist, kws_result *out, FlatOut *flat) {
   Engine &E = g->eng;
   const kws_options &o = g->opt;
   const int32_t n = g->n;
@@ -882,9 +1005,18 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   pack(qs, qa, qb, o.share_lanes >= 0 && !export_only, pk);
   const int W = (int)pk.word_used.size();
   if (W > max_words) return PASS_TOO_WIDE;
-  int T = std::max(1, o.tile_words);
-  if (export_only) T = 1;
-  T = std::min(T, pow2ceil(W));
+  int T = 1;
+  if (!export_only) {
+    // pull gathers one 8T-byte piece per edge and tile (at least a 64-byte
+    // line), the streaming kernels touch every padded word of every vertex
+    double best = 0;
+    for (int t = 1; t <= std::max(1, o.tile_words); t <<= 1) {
+      const double tl = (W + t - 1) / t;
+      const double cost = (double)g->m * tl * (4.0 + std::max(8.0 * t, 64.0)) +
+                          (double)n * tl * t * 8.0 * 3.0 * 2.0;
+      if (t == 1 || cost <= best) { best = cost; T = t; }
+    }
+  }
   const int tiles = (W + T - 1) / T, Wp = tiles * T;
   int D = 0;
   for (int q = qa; q < qb; q++) D = std::max(D, qs[q].dmax);
@@ -922,6 +1054,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   std::vector<int32_t> q_dmax(nq), q_nk(nq), q_kcap(nq), q_hoff(nq), q_coff(nq), q_ccap(nq), q_roff(nq + 1),
       q_kdoff(nq), q_eoff(nq), q_ecap(nq), q_boff(nq);
   std::vector<uint8_t> bits;
+  std::vector<int32_t> qlanes;
   int64_t nhist = 0, ncand = 0, nslots = 0, nkd = 0, nedge = 0;
   for (int i = 0; i < nq; i++) {
     const QIn &Q = qs[qa + i];
@@ -942,6 +1075,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
     nedge += (int64_t)q_kcap[i] * q_ecap[i];
     q_boff[i] = (int32_t)bits.size();
     bits.insert(bits.end(), pk.q_bits[i].begin(), pk.q_bits[i].begin() + Q.nk);
+    qlanes.insert(qlanes.end(), pk.q_lanes[i].begin(), pk.q_lanes[i].begin() + Q.nk);
   }
   q_roff[nq] = (int32_t)nslots;
   if (nhist > INT32_MAX / 2 || ncand > INT32_MAX / 2 || nedge > INT32_MAX / 2 || nkd > INT32_MAX / 2)
@@ -961,7 +1095,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
                o_qcoff = pl.add((size_t)nq * 4), o_qccap = pl.add((size_t)nq * 4),
                o_qroff = pl.add((size_t)(nq + 1) * 4), o_qkdoff = pl.add((size_t)nq * 4),
                o_qeoff = pl.add((size_t)nq * 4), o_qecap = pl.add((size_t)nq * 4), o_qboff = pl.add((size_t)nq * 4),
-               o_bits = pl.add(bits.size() + 1);
+               o_bits = pl.add(bits.size() + 1), o_qlanes = pl.add(qlanes.size() * 4 + 4);
   KWS_TRY(E.h_plan.ensure(pl.size, "plan (host)"));
   KWS_TRY(E.plan.ensure(pl.size, "plan"));
   uint8_t *hp = E.h_plan.as<uint8_t>();
@@ -987,6 +1121,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   put(o_qecap, q_ecap.data(), (size_t)nq * 4);
   put(o_qboff, q_boff.data(), (size_t)nq * 4);
   put(o_bits, bits.data(), bits.size());
+  put(o_qlanes, qlanes.data(), qlanes.size() * 4);
 
   // ---------------- result arena (D2H) and zeroed scratch
   Layout al;
@@ -1012,7 +1147,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   P.n = n; P.tiles = tiles; P.Wp = Wp; P.G = std::min(64, pow2ceil(Wp)); P.D = D; P.B = B;
   P.nq = nq; P.n_lanes = n_lanes; P.chunks = chunks; P.CH = CH; P.nhist = (int32_t)nhist;
   P.hist_lds = hist_lds; P.te_lds = te_lds; P.force_dir = o.direction; P.alpha = o.alpha;
-  P.total_seeds = seed_off[n_lanes]; P.n_hub = g->n_hub; P.total_slots = nslots;
+  P.total_seeds = seed_off[n_lanes]; P.n_hub = g->n_hub; P.total_slots = nslots; P.total_kd = nkd;
   for (int b = 0; b <= BIN_COUNT; b++) P.bin_begin[b] = g->bin_begin[b];
   P.pstride = (size_t)n * Wp;
   P.fwd_ptr = g->fwd_ptr; P.fwd_col = g->fwd_col; P.rev_ptr = g->rev_ptr; P.rev_col = g->rev_col;
@@ -1042,6 +1177,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   P.q_ecap = (const int32_t *)(dp + o_qecap);
   P.q_boff = (const int32_t *)(dp + o_qboff);
   P.bits = dp + o_bits;
+  P.q_lane = (const int32_t *)(dp + o_qlanes);
   uint8_t *ar = E.arena.as<uint8_t>();
   uint8_t *zr = E.zero_region.as<uint8_t>();
   P.zero0 = (uint64_t *)ar; P.zero0_words = (int64_t)(a_zero_end / 8);
@@ -1098,8 +1234,26 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   const int2 *h_edges = (const int2 *)(ha + a_edges);
   for (int i = 0; i < nq; i++) {
     const QIn &Q = qs[qa + i];
-    kws_result &r = out[qa + i];
     const int nr = h_nroots[i];
+    if (flat) {
+      FlatOut &F = *flat;
+      F.kw.insert(F.kw.end(), Q.kw, Q.kw + Q.nk);
+      F.kw_ptr.push_back((int64_t)F.kw.size());
+      F.roots.insert(F.roots.end(), h_roots + q_roff[i], h_roots + q_roff[i] + nr);
+      F.scores.insert(F.scores.end(), h_scores + q_roff[i], h_scores + q_roff[i] + nr);
+      F.root_ptr.push_back((int64_t)F.roots.size());
+      F.kw_dist.insert(F.kw_dist.end(), h_kwdist + q_kdoff[i], h_kwdist + q_kdoff[i] + (size_t)nr * Q.nk);
+      F.dist_ptr.push_back((int64_t)F.kw_dist.size());
+      for (int j = 0; j < nr; j++) {
+        const int c = h_ecount[q_roff[i] + j];
+        const int2 *src = h_edges + q_eoff[i] + (size_t)j * q_ecap[i];
+        for (int t = 0; t < c; t++) { F.edge_src.push_back(src[t].x); F.edge_dst.push_back(src[t].y); }
+        F.edge_ptr.push_back((int64_t)F.edge_src.size());
+      }
+      F.te.push_back((int64_t)h_te[i]);
+      continue;
+    }
+    kws_result &r = out[qa + i];
     r.n_roots = nr;
     r.n_kw = Q.nk;
     r.te = (int64_t)h_te[i];
@@ -1160,16 +1314,17 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
 void default_options(kws_options *o) {
   std::memset(o, 0, sizeof(*o));
   o->direction = 0;
-  o->alpha = 1.0f;
+  o->alpha = 8.0f;
   o->tile_words = 8;
   o->block = BLOCK;
   o->use_graph = 0;
   o->share_lanes = 1;
 }
 
-kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out) {
-  if (!g || (!qs && nq > 0) || (!out && nq > 0) || nq < 0) return fail(KWS_EINVAL, "null argument");
-  for (int i = 0; i < nq; i++) std::memset(&out[i], 0, sizeof(kws_result));
+kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out, FlatOut *flat) {
+  if (!g || (!qs && nq > 0) || (!out && !flat && nq > 0) || nq < 0) return fail(KWS_EINVAL, "null argument");
+  if (out)
+    for (int i = 0; i < nq; i++) std::memset(&out[i], 0, sizeof(kws_result));
   std::vector<QIn> in(nq);
   for (int i = 0; i < nq; i++) {
     const kws_query &q = qs[i];
@@ -1206,12 +1361,13 @@ kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out
     if (qb == qa) return fail(KWS_ENOMEM, "device memory budget too small for one query");
     kws_status st;
     for (;;) {
-      st = run_pass(g, in, qa, qb, max_words, false, nullptr, out);
+      st = run_pass(g, in, qa, qb, max_words, false, nullptr, out, flat);
       if (st != PASS_TOO_WIDE) break;
       qb = qa + std::max(1, (qb - qa) * 7 / 8);
     }
     if (st != KWS_OK) {
-      for (int i = 0; i < nq; i++) kws_result_free(&out[i]);
+      if (out)
+        for (int i = 0; i < nq; i++) kws_result_free(&out[i]);
       g->eng.state_words = 0;   // force a clean reallocation (nxt must start at zero)
       return st;
     }
@@ -1227,7 +1383,7 @@ kws_status debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dis
   if (d_max < 0 || d_max > KWS_MAX_DMAX) return fail(KWS_EINVAL, "d_max %d outside 0..%d", d_max, KWS_MAX_DMAX);
   std::vector<QIn> in(1);
   in[0].nk = 1; in[0].dmax = d_max; in[0].k = 0; in[0].kw[0] = kw;
-  kws_status st = run_pass(g, in, 0, 1, 1, true, dist, nullptr);
+  kws_status st = run_pass(g, in, 0, 1, 1, true, dist, nullptr, nullptr);
   if (st != KWS_OK) g->eng.state_words = 0;
   return st;
 }

@@ -48,6 +48,15 @@ class ResultC(C.Structure):
                 ("te", C.c_int64)]
 
 
+class BatchResultC(C.Structure):
+    _fields_ = [("nq", C.c_int32), ("total_roots", C.c_int64), ("root_ptr", C.POINTER(C.c_int64)),
+                ("roots", C.POINTER(C.c_int32)), ("scores", C.POINTER(C.c_int32)),
+                ("kw_ptr", C.POINTER(C.c_int64)), ("kw", C.POINTER(C.c_int32)),
+                ("dist_ptr", C.POINTER(C.c_int64)), ("kw_dist", C.POINTER(C.c_uint8)),
+                ("edge_ptr", C.POINTER(C.c_int64)), ("edge_src", C.POINTER(C.c_int32)),
+                ("edge_dst", C.POINTER(C.c_int32)), ("te", C.POINTER(C.c_int64))]
+
+
 class Options(C.Structure):
     _fields_ = [("direction", C.c_int32), ("alpha", C.c_float), ("tile_words", C.c_int32),
                 ("block", C.c_int32), ("use_graph", C.c_int32), ("share_lanes", C.c_int32)]
@@ -97,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "kws_keyword_search": (C.c_int, [P, C.POINTER(QueryC), C.POINTER(ResultC)]),
         "kws_search_batch": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.POINTER(ResultC)]),
         "kws_result_free": (None, [C.POINTER(ResultC)]),
+        "kws_search_batch_flat": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.POINTER(BatchResultC)]),
+        "kws_batch_result_free": (None, [C.POINTER(BatchResultC)]),
         "kws_debug_distances": (C.c_int, [P, C.c_int32, C.c_int32, P]),
         "kws_set_options": (C.c_int, [P, C.POINTER(Options)]),
         "kws_get_options": (C.c_int, [P, C.POINTER(Options)]),
@@ -226,7 +237,8 @@ class Graph:
         finally:
             self._lib.kws_result_free(C.byref(r))
 
-    def search_batch(self, queries) -> List[Result]:
+    def search_batch_each(self, queries) -> List[Result]:
+        """kws_search_batch: one separately allocated result per query."""
         qa, keep = _queries(queries)
         n = len(queries)
         rs = (ResultC * max(1, n))()
@@ -236,6 +248,47 @@ class Graph:
         finally:
             for i in range(n):
                 self._lib.kws_result_free(C.byref(rs[i]))
+
+    def search_batch_flat(self, queries) -> dict:
+        """kws_search_batch_flat: the whole batch as flat numpy arrays."""
+        qa, keep = _queries(queries)
+        n = len(queries)
+        r = BatchResultC()
+        _check(self._lib.kws_search_batch_flat(self.h, qa, n, C.byref(r)))
+        try:
+            nr = int(r.total_roots)
+
+            def arr(ptr, count, dt):
+                if count == 0:
+                    return np.zeros(0, dt)
+                return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+            root_ptr = arr(r.root_ptr, n + 1, np.int64)
+            kw_ptr = arr(r.kw_ptr, n + 1, np.int64)
+            dist_ptr = arr(r.dist_ptr, n + 1, np.int64)
+            edge_ptr = arr(r.edge_ptr, nr + 1, np.int64)
+            ne = int(edge_ptr[-1]) if nr else 0
+            return dict(root_ptr=root_ptr, roots=arr(r.roots, nr, np.int32), scores=arr(r.scores, nr, np.int32),
+                        kw_ptr=kw_ptr, kw=arr(r.kw, int(kw_ptr[-1]), np.int32), dist_ptr=dist_ptr,
+                        kw_dist=arr(r.kw_dist, int(dist_ptr[-1]), np.uint8), edge_ptr=edge_ptr,
+                        edge_src=arr(r.edge_src, ne, np.int32), edge_dst=arr(r.edge_dst, ne, np.int32),
+                        te=arr(r.te, n, np.int64))
+        finally:
+            self._lib.kws_batch_result_free(C.byref(r))
+
+    def search_batch(self, queries) -> List[Result]:
+        """Batched search; per-query Result views cut from the flat output."""
+        f = self.search_batch_flat(queries)
+        out = []
+        for q in range(len(queries)):
+            a, b = int(f["root_ptr"][q]), int(f["root_ptr"][q + 1])
+            kw = f["kw"][f["kw_ptr"][q]:f["kw_ptr"][q + 1]]
+            kd = f["kw_dist"][f["dist_ptr"][q]:f["dist_ptr"][q + 1]].reshape(b - a, kw.shape[0])
+            ep = f["edge_ptr"][a:b + 1]
+            e0, e1 = int(ep[0]), int(ep[-1])
+            out.append(Result([int(x) for x in kw], f["roots"][a:b], f["scores"][a:b], kd, ep - e0,
+                              f["edge_src"][e0:e1], f["edge_dst"][e0:e1], int(f["te"][q])))
+        return out
 
     def debug_distances(self, kw: int, d_max: int) -> np.ndarray:
         n = self.info().n

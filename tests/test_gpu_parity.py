@@ -70,6 +70,7 @@ def test_tiny_random(K, block):
             G.set_options(direction=direction, tile_words=[1, 2, 4, 8, 16][seed % 5],
                           share_lanes=1 if seed % 2 else -1)
             assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction}")
+        assert_all_same(G.search_batch_each(qs), want, f"tiny {seed} batch (per-query results)")
         G.close()
 
 
@@ -237,3 +238,32 @@ def test_errors(K, chunglu):
     r = G.keyword_search(list(range(64)), 1, 5)
     w = o.search(list(range(64)), 1, 5)
     assert_same(r, w, "64 keywords")
+
+
+def test_unsorted_rows_and_multi_edges(K):
+    # rows given in arbitrary order (with repeated edges) must give the same answers
+    g = workloads.chunglu10k()
+    rng = np.random.default_rng(5)
+    col = g.col.copy()
+    for u in range(g.n):
+        a, b = g.row_ptr[u], g.row_ptr[u + 1]
+        col[a:b] = rng.permutation(col[a:b])
+    from synth.gen import Graph as SG
+    # repeat the first out-edge of every 7th vertex
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    extra = np.flatnonzero(np.diff(g.row_ptr) > 0)[::7]
+    rows = [list(col[g.row_ptr[u]:g.row_ptr[u + 1]]) for u in range(g.n)]
+    for u in extra:
+        rows[u].append(rows[u][0])
+    rp = np.zeros(g.n + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col2 = np.array([x for r in rows for x in r], np.int32)
+    g2 = SG(rp, col2, g.n_labels, g.lab_ptr, g.lab, None, "chunglu_unsorted")
+    qs = workloads.chunglu10k_queries(40)
+    want = oracle_results(oracle.Oracle(g2), qs)
+    G = K.Graph.from_synth(g2)
+    say("unsorted rows")
+    assert_all_same(G.search_batch(qs), want, "unsorted batch")
+    for i in range(0, 40, 5):
+        assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"unsorted plain {i}")
+    G.close()
