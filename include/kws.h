@@ -170,6 +170,22 @@ typedef struct {
 kws_status kws_set_options(kws_graph *g, const kws_options *opt);
 kws_status kws_get_options(kws_graph *g, kws_options *opt);
 
+/* Autotuner: runs the sample batch under a grid of tile widths and
+ * push/pull policies (median of `reps` timed runs after one warm-up each),
+ * checks that every configuration returns identical answers (KWS_EDEVICE
+ * if not), sets the fastest as the handle's options and returns it in
+ * *best (may be NULL). With cache_path, a previous choice for the same graph
+ * and batch shape is reused without timing, and new choices are appended.
+ * budget_ms > 0 stops trying new configurations once exceeded. */
+typedef struct {
+  int32_t configs_tried;
+  double best_ms;           /* median time of the sample batch with the choice */
+  double default_ms;        /* same with the default options */
+  int32_t from_cache;
+} kws_tune_report;
+kws_status kws_autotune(kws_graph *g, const kws_query *sample, int32_t nq, int32_t reps, double budget_ms,
+                        const char *cache_path, kws_options *best, kws_tune_report *report);
+
 /* Runs device work on this stream (a hipStream_t, e.g. from
  * torch.cuda.Stream().cuda_stream). NULL restores the handle's own stream.
  * The stream must be a default-priority stream. */
@@ -226,6 +242,47 @@ typedef struct {
   int64_t unfinished_edges[KWS_MAX_DMAX + 1];
 } kws_batch_stats;
 kws_status kws_last_batch_stats(kws_graph *g, kws_batch_stats *st);
+
+/* ---------------------------------------------------------------- serving
+ * A server keeps the graph resident and runs a device loop on its own
+ * thread and stream. Submitted queries wait in an admission queue; at every
+ * device step the loop packs waiting queries into free 64-lane word slots
+ * (their per-query state memory: one lane per distinct keyword, the slot
+ * count fixed by the memory budget), seeds them, and advances every occupied
+ * slot by one BFS level, each slot at its own level. A slot whose radius is
+ * reached is scored, ranked and answered; its tickets complete and the slot
+ * is reused. Results equal those of kws_keyword_search for the same query.
+ * The graph must outlive its servers. */
+typedef struct kws_server kws_server;
+typedef struct {
+  int32_t max_words;       /* word slots; 0 = as many as mem_bytes allows (at most 1024) */
+  int32_t max_dmax;        /* largest d_max accepted (sizes the distance planes); 0 = 15 */
+  int32_t queue_capacity;  /* waiting queries before submit returns KWS_EBUSY; 0 = 65536 */
+  int32_t tile_words;      /* words per vertex per tile (1, 2, 4, 8, 16); 0 = 8 */
+  int64_t mem_bytes;       /* device bytes for the search state; 0 = the graph's budget */
+} kws_server_opts;
+kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_server **out);
+/* Non-blocking. *ticket identifies the query. KWS_EBUSY when the queue is full. */
+kws_status kws_server_submit(kws_server *s, const kws_query *q, uint64_t *ticket);
+/* *done = 1: the result moved into *out (caller frees it with kws_result_free)
+ * and the ticket is released. *done = 0: still running. KWS_ECANCELLED for a
+ * cancelled ticket (then released); KWS_EINVAL for an unknown ticket. */
+kws_status kws_server_poll(kws_server *s, uint64_t ticket, kws_result *out, int32_t *done);
+/* Like poll, but waits up to timeout_us microseconds (< 0: no limit). */
+kws_status kws_server_wait(kws_server *s, uint64_t ticket, int64_t timeout_us, kws_result *out, int32_t *done);
+/* A queued query is dropped; a running one finishes and its result is discarded. */
+kws_status kws_server_cancel(kws_server *s, uint64_t ticket);
+typedef struct {
+  int64_t submitted, completed, cancelled, rejected, steps;
+  int32_t queued, active_words, max_words;
+  double elapsed_s;        /* first submit to last completion */
+  double qps;              /* completed / elapsed_s */
+  double p50_us, p99_us;   /* submit-to-completion latency of completed queries */
+  double mean_active_words;/* occupied slots per device step */
+} kws_server_stats;
+kws_status kws_server_stats_get(kws_server *s, kws_server_stats *st);
+/* Stops admission, cancels queued queries, lets running slots finish, joins. */
+void kws_server_destroy(kws_server *s);
 
 /* Thread-local text for the last non-OK status returned on this thread. */
 const char *kws_last_error(void);

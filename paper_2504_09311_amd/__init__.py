@@ -4,6 +4,6 @@ The hot path lives in the HIP library ``libkws.so`` (C ABI in
 ``include/kws.h``); ``kws`` is its ctypes binding.
 """
 from .kws import (  # noqa: F401
-    Graph, Result, KwsError, load_library, declared_symbols, last_error, set_allocator_torch,
+    Graph, Server, Result, KwsError, load_library, declared_symbols, last_error, set_allocator_torch,
     OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EBUSY, ECANCELLED, MAX_KW, MAX_DMAX, MAX_K, DIST_INF,
 )

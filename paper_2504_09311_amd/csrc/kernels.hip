@@ -1,0 +1,820 @@
+// Device kernels of the keyword search and their launchers: seeding,
+// level expansion by push (64-bit atomicOr into in-neighbours) or pull
+// (each vertex missing lanes ORs its out-neighbours' frontier masks, no
+// atomics, early exit), finalize with frontier compaction, root filter and
+// score histogram, exact top-k with id-ordered ties, answer-graph walk.
+//
+// The push/pull choice is made on the device from the statistics the
+// previous finalize wrote, so the launch sequence never depends on data.
+#include <algorithm>
+
+#include "pass.h"
+
+namespace kws {
+
+__device__ __forceinline__ int pick_dir(const uint64_t *st, float alpha, int force) {
+  const uint64_t packed = st[0];
+  const uint32_t nf = (uint32_t)(packed >> 32), mf = (uint32_t)packed;
+  if (nf == 0) return 0;                       // empty frontier: nothing to expand
+  if (force == 1 || force == 2) return force;
+  return (double)alpha * (double)mf > (double)st[1] ? 2 : 1;   // 1 push, 2 pull
+}
+
+__device__ __forceinline__ uint64_t group_bits(int lane, int S) {
+  return S >= 64 ? ~0ull : (((1ull << S) - 1ull) << (lane & ~(S - 1)));
+}
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    int32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Block-wide exclusive scan of x; *total receives the block sum.
+__device__ int32_t block_scan(int32_t x, int32_t *total) {
+  __shared__ int32_t s_w[BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int32_t incl = wave_incl_scan(x, lane);
+  if (lane == 63) s_w[wid] = incl;
+  __syncthreads();
+  int32_t base = 0, all = 0;
+  for (int w = 0; w < BLOCK / 64; w++) {
+    base += w < wid ? s_w[w] : 0;
+    all += s_w[w];
+  }
+  __syncthreads();
+  *total = all;
+  return base + incl - x;
+}
+
+// ---- seed: zero the per-pass counters; OR each lane's bit into nxt of its keyword vertices
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
+  const int64_t gid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, gsz = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
+  for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
+  for (int64_t i = gid; i < P.zero2_words; i += gsz) P.zero2[i] = 0;
+  for (int64_t i = gid; i < P.total_seeds; i += gsz) {
+    int lo = 0, hi = P.n_lanes;               // largest lane with lane_seed_off[lane] <= i
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (P.lane_seed_off[mid] <= i) lo = mid; else hi = mid;
+    }
+    const int32_t v = P.inv_vtx[P.lane_seed_begin[lo] + (int32_t)(i - P.lane_seed_off[lo])];
+    const int word = P.lane_word[lo];
+    const size_t idx = ((size_t)(word / T) * P.n + v) * T + (word % T);
+    atomicOr((unsigned long long *)&P.nxt[idx], 1ull << P.lane_bit[lo]);
+  }
+}
+
+// ---- finalize one step: new = nxt & ~vis & act_new; vis |= new; distance planes; next frontier
+// buffer; nxt cleared; the statistics that pick the direction of the next
+// level. Frontier vertices are compacted into LDS per chunk of FIN_CHUNK
+// vertices (wavefront ballot + prefix sums), then one atomic per chunk
+// reserves their place in the global list and its in-edge offsets.
+constexpr int FIN_CHUNK = 512;
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) {
+  extern __shared__ uint64_t s_live[];                    // [Wp]
+  __shared__ int32_t s_lv[FIN_CHUNK], s_le[FIN_CHUNK];
+  __shared__ int32_t s_wcnt[BLOCK / 64], s_wedge[BLOCK / 64];
+  __shared__ int32_t s_cnt, s_edges;
+  __shared__ uint64_t s_base;
+  constexpr int G = T, VPB = BLOCK / T;   // T threads per vertex, one per word of a tile
+  const int tid = threadIdx.x, gl = tid & (G - 1), lane = tid & 63, wid = tid >> 6;
+  const uint64_t gmask = group_bits(lane, G);
+  uint64_t *st = S.st_out;
+  for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
+  uint64_t mu_acc = 0;
+  const int64_t nchunks = ((int64_t)P.n + FIN_CHUNK - 1) / FIN_CHUNK;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (tid == 0) { s_cnt = 0; s_edges = 0; }
+    __syncthreads();
+    const int64_t c0 = c * FIN_CHUNK, c1 = min((int64_t)P.n, c0 + FIN_CHUNK);
+    for (int64_t vb = c0; vb < c1; vb += VPB) {
+      const int64_t v = vb + tid / G;
+      const bool valid = v < c1;
+      uint64_t anyf = 0, anyneed = 0;
+      if (valid) {
+        constexpr int TG = 8;   // tiles whose words are loaded before any store
+        for (int t0 = 0; t0 < P.tiles; t0 += TG) {
+          uint64_t nxv[TG], oldv[TG];
+#pragma unroll
+          for (int k = 0; k < TG; k++) {
+            const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
+            nxv[k] = t0 + k < P.tiles ? P.nxt[idx] : 0ull;
+            oldv[k] = t0 + k < P.tiles ? P.vis[idx] : 0ull;
+          }
+#pragma unroll
+          for (int k = 0; k < TG; k++) {
+            if (t0 + k >= P.tiles) break;
+            const int j = (t0 + k) * T + gl;
+            const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
+            const uint64_t nx = nxv[k];
+            const int nl = S.newlvl[j];
+            const uint64_t old = nl ? oldv[k] : 0ull;
+            const uint64_t fnew = nx & ~old & S.act_new[j];
+            const uint64_t nv = old | fnew;
+            if (nl == 0) {
+              P.vis[idx] = nv;
+              for (int b = 0; b < P.B; b++) P.planes[b * P.pstride + idx] = 0;
+            } else if (fnew) {
+              P.vis[idx] = nv;
+              for (int b = 0; b < P.B; b++)
+                if ((nl >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
+            }
+            if (S.write_next) {
+              S.fr_next[idx] = fnew;
+              if (fnew) atomicOr((unsigned long long *)&s_live[j], fnew);
+              anyneed |= S.act_nn[j] & ~nv;
+            }
+            if (nx) P.nxt[idx] = 0;
+            anyf |= fnew;
+          }
+        }
+      }
+      const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
+      const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
+      const bool take = valid && gl == 0 && fflag;
+      if (valid && gl == 0 && nflag) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
+      const int32_t indeg = take ? P.rev_ptr[v + 1] - P.rev_ptr[v] : 0;
+      const uint64_t bal = __ballot(take);
+      const int32_t wpre = __popcll(bal & ((1ull << lane) - 1ull));
+      const int32_t eincl = wave_incl_scan(indeg, lane);
+      if (lane == 63) { s_wcnt[wid] = __popcll(bal); s_wedge[wid] = eincl; }
+      __syncthreads();
+      if (take) {
+        int32_t cpre = s_cnt, epre = s_edges;
+        for (int w = 0; w < wid; w++) { cpre += s_wcnt[w]; epre += s_wedge[w]; }
+        s_lv[cpre + wpre] = (int32_t)v;
+        s_le[cpre + wpre] = epre + eincl - indeg;
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int w = 0; w < BLOCK / 64; w++) { s_cnt += s_wcnt[w]; s_edges += s_wedge[w]; }
+      __syncthreads();
+    }
+    if (tid == 0)
+      s_base = s_cnt ? atomicAdd((unsigned long long *)&st[0],
+                                 (unsigned long long)(((uint64_t)s_cnt << 32) | (uint32_t)s_edges))
+                     : 0ull;
+    __syncthreads();
+    if (S.build_list) {
+      const int32_t bc = (int32_t)(s_base >> 32), be = (int32_t)(uint32_t)s_base;
+      for (int i = tid; i < s_cnt; i += BLOCK) {
+        P.flist[bc + i] = s_lv[i];
+        P.flist_eoff[bc + i] = be + s_le[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (S.write_next) {
+    __syncthreads();
+    for (int j = tid; j < P.Wp; j += BLOCK)
+      if (s_live[j]) atomicOr((unsigned long long *)&S.live_out[j], s_live[j]);
+    for (int off = 32; off > 0; off >>= 1) mu_acc += __shfl_xor(mu_acc, off);
+    if (lane == 0 && mu_acc) atomicAdd((unsigned long long *)&st[1], (unsigned long long)mu_acc);
+  }
+}
+
+// ---- push: every frontier in-edge (p -> v) ORs v's frontier lanes into nxt[p]
+// Wq threads per edge cover the words (power of two, <= 64).
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_push(const Pass P, const Step S, int Wq) {
+  const uint64_t *st = S.st_in;
+  if (pick_dir(st, P.alpha, P.force_dir) != 1) return;
+  const int32_t nf = (int32_t)(st[0] >> 32);
+  const int64_t mf = (int64_t)(uint32_t)st[0];
+  const int EPB = BLOCK / Wq;
+  const int tid = threadIdx.x, wq = tid & (Wq - 1), es = tid / Wq;
+  const uint64_t *fr = S.fr_cur;
+  const uint64_t *act = S.act_exp;
+  const uint64_t *live = S.live_in;
+  __shared__ int32_t s_j;
+  for (int64_t eb = (int64_t)blockIdx.x * EPB; eb < mf; eb += (int64_t)gridDim.x * EPB) {
+    if (tid == 0) {
+      int32_t lo = 0, hi = nf;                // largest j with flist_eoff[j] <= eb
+      while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (P.flist_eoff[mid] <= eb) lo = mid; else hi = mid;
+      }
+      s_j = lo;
+    }
+    __syncthreads();
+    int32_t j = s_j;
+    __syncthreads();
+    const int64_t e = eb + es;
+    if (e >= mf) continue;
+    while (j + 1 < nf && P.flist_eoff[j + 1] <= e) j++;
+    const int32_t v = P.flist[j];
+    const int32_t p = P.rev_col[P.rev_ptr[v] + (int32_t)(e - P.flist_eoff[j])];
+    for (int word = wq; word < P.Wp; word += Wq) {
+      const size_t tb = (size_t)(word / T) * P.n * T;
+      const int w = word % T;
+      uint64_t f = fr[tb + (size_t)v * T + w] & act[word] & live[word];
+      if (!f) continue;
+      f &= ~P.vis[tb + (size_t)p * T + w];
+      if (f) atomicOr((unsigned long long *)&P.nxt[tb + (size_t)p * T + w], f);
+    }
+  }
+}
+
+// ---- pull: a group of S = T*E threads owns one row (or one hub chunk);
+// thread (e, w) ORs word w of the frontier mask of every E-th out-neighbour.
+// Early exit once the group has found every lane the vertex still misses.
+template <int T, int S, bool SEG>
+__device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
+                                          int tile, int bb, int bpt) {
+  constexpr int E = S / T, GPB = BLOCK / S, U = 4;
+  const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
+  const uint64_t gmask = group_bits(lane, S);
+  const size_t tb = (size_t)tile * P.n * T;
+  const uint64_t *fr = SP.fr_cur + tb;
+  const uint64_t *vis = P.vis + tb;
+  uint64_t *nxt = P.nxt + tb;
+  const int word = tile * T + w;
+  const uint64_t actw = SP.act_exp[word] & SP.live_in[word];
+  const int32_t *col = P.fwd_col;
+  for (int64_t it = (int64_t)bb * GPB + tid / S; it < n_items; it += (int64_t)bpt * GPB) {
+    int32_t v, eb, ee;
+    if (SEG) {
+      v = P.hub_v[it]; eb = P.hub_b[it]; ee = P.hub_e[it];
+    } else {
+      v = items[it]; eb = P.fwd_ptr[v]; ee = P.fwd_ptr[v + 1];
+    }
+    const uint64_t need = actw & ~vis[(size_t)v * T + w];
+    if ((__ballot(need != 0) & gmask) == 0) continue;
+    uint64_t acc = 0;
+    for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
+      int32_t x[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int32_t e = e0 + u * E + eo;
+        x[u] = e < ee ? col[e] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
+      uint64_t r = acc;
+#pragma unroll
+      for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
+      if ((__ballot((r & need) != need) & gmask) == 0) break;
+    }
+#pragma unroll
+    for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
+    acc &= need;
+    if (eo == 0 && acc) {
+      if (SEG) atomicOr((unsigned long long *)&nxt[(size_t)v * T + w], acc);
+      else nxt[(size_t)v * T + w] = acc;
+    }
+  }
+}
+
+// One launch covers every degree bin: blocks [boff[b], boff[b+1]) serve bin b
+// (b = 3 is the hub chunks), tiles x blocks-per-tile inside each range.
+struct PullGrid { int32_t boff[BIN_COUNT + 2]; };
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, const PullGrid pg) {
+  if (pick_dir(S.st_in, P.alpha, P.force_dir) != 2) return;
+  constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
+  const int bid = blockIdx.x;
+  if (bid >= pg.boff[BIN_COUNT + 1]) return;   // the grid has one block even when every bin is empty
+  int b = 0;
+  while (b < BIN_COUNT && bid >= pg.boff[b + 1]) b++;
+  const int nblk = pg.boff[b + 1] - pg.boff[b];
+  const int bpt = nblk / P.tiles, lb = bid - pg.boff[b];
+  const int tile = lb / bpt, bb = lb % bpt;
+  if (tile >= P.tiles) return;
+  if (b == BIN_COUNT) {
+    pull_rows<T, 64, true>(P, S, nullptr, P.n_hub, tile, bb, bpt);
+    return;
+  }
+  const int32_t *items = P.bin_vtx + P.bin_begin[b];
+  const int64_t n_items = P.bin_begin[b + 1] - P.bin_begin[b];
+  if (b == BIN_SMALL) pull_rows<T, S_SMALL, false>(P, S, items, n_items, tile, bb, bpt);
+  else if (b == BIN_MEDIUM) pull_rows<T, S_MED, false>(P, S, items, n_items, tile, bb, bpt);
+  else pull_rows<T, 64, false>(P, S, items, n_items, tile, bb, bpt);
+}
+
+// ---- score: per vertex and query, root test, score histogram per chunk and
+// the scanned-edge count te (in-degree of every vertex each lane expanded).
+// Each thread holds SC_R vertices; a wavefront walks the words and their
+// queries in lockstep, so histogram updates are aggregated per distinct
+// score value and te is reduced across the wavefront once per query.
+constexpr int SC_R = 2;
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
+  extern __shared__ uint64_t s_dyn[];
+  uint64_t *s_te = s_dyn;
+  int32_t *s_hist = (int32_t *)(s_dyn + (P.te_lds ? P.nq : 0));
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int split = (P.CH + BLOCK * SC_R - 1) / (BLOCK * SC_R);
+  if (P.te_lds)
+    for (int i = tid; i < P.nq; i += BLOCK) s_te[i] = 0;
+  for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
+    const int c = (int)(bid / split), part = (int)(bid % split);
+    if (P.hist_lds)
+      for (int i = tid; i < P.nhist; i += BLOCK) s_hist[i] = 0;
+    __syncthreads();
+    int32_t *hist = P.hist_lds ? s_hist : P.hist + (size_t)c * P.nhist;
+    const int64_t cend = min((int64_t)P.n, (int64_t)(c + 1) * P.CH);
+    const int64_t v0 = (int64_t)c * P.CH + (int64_t)part * BLOCK * SC_R;
+    int64_t vv[SC_R];
+    uint64_t indeg[SC_R];
+#pragma unroll
+    for (int r = 0; r < SC_R; r++) {
+      vv[r] = v0 + r * BLOCK + tid;
+      indeg[r] = vv[r] < cend ? (uint64_t)(P.rev_ptr[vv[r] + 1] - P.rev_ptr[vv[r]]) : 0ull;
+    }
+    for (int j = 0; j < P.Wp; j++) {
+      const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
+      if (qb == qe) continue;
+      const size_t base = (size_t)(j / T) * P.n * T + (j % T);
+      uint64_t vis[SC_R], pl[SC_R][4];
+      bool any = false;
+#pragma unroll
+      for (int r = 0; r < SC_R; r++) {
+        vis[r] = vv[r] < cend ? P.vis[base + (size_t)vv[r] * T] : 0ull;
+        for (int b = 0; b < 4; b++)
+          pl[r][b] = (b < P.B && vis[r]) ? P.planes[b * P.pstride + base + (size_t)vv[r] * T] : 0ull;
+        any |= vis[r] != 0;
+      }
+      if (__ballot(any) == 0) continue;
+      for (int qi = qb; qi < qe; qi++) {
+        const int q = P.word_q[qi];
+        const uint64_t m = P.q_mask[q];
+        const int dq = P.q_dmax[q], hq = P.q_hoff[q];
+        uint64_t t = 0;
+#pragma unroll
+        for (int r = 0; r < SC_R; r++) {
+          const uint64_t x = vis[r] & m;
+          uint64_t eq = x;
+          for (int b = 0; b < P.B; b++) eq &= ((dq >> b) & 1) ? pl[r][b] : ~pl[r][b];
+          t += (uint64_t)(__popcll(x) - __popcll(eq)) * indeg[r];
+          const bool root = x == m;
+          int sc = 0;
+          if (root)
+            for (int b = 0; b < P.B; b++) sc += __popcll(pl[r][b] & m) << b;
+          uint64_t pend = __ballot(root);
+          while (pend) {
+            const int leader = __ffsll((long long)pend) - 1;
+            const int sv = __shfl(sc, leader);
+            const uint64_t same = __ballot(root && sc == sv);
+            if (lane == leader) atomicAdd(&hist[hq + sv], (int)__popcll(same));
+            pend &= ~same;
+          }
+        }
+        if (__ballot(t != 0)) {
+          for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+          if (lane == 0) {
+            if (P.te_lds) atomicAdd((unsigned long long *)&s_te[q], (unsigned long long)t);
+            else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (P.hist_lds)
+      for (int i = tid; i < P.nhist; i += BLOCK)
+        if (s_hist[i]) atomicAdd(&P.hist[(size_t)c * P.nhist + i], s_hist[i]);
+    __syncthreads();
+  }
+  if (P.te_lds) {
+    __syncthreads();
+    for (int i = tid; i < P.nq; i += BLOCK)
+      if (s_te[i]) atomicAdd((unsigned long long *)&P.te[i], (unsigned long long)s_te[i]);
+  }
+}
+
+// ---- threshold: per query, the score s* of the k-th root, how many ties at
+// s* to take, and one work item per chunk that holds a selected root.
+__global__ __launch_bounds__(BLOCK) void k_threshold(const Pass P) {
+  __shared__ int32_t tot[KWS_MAX_KW * KWS_MAX_DMAX + 1];
+  __shared__ int32_t s_sel[4];
+  const int tid = threadIdx.x;
+  for (int q = blockIdx.x; q < P.nq; q += gridDim.x) {
+    const int S1 = P.q_nk[q] * P.q_dmax[q] + 1, hoff = P.q_hoff[q];
+    for (int s = tid; s < S1; s += BLOCK) tot[s] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < (int64_t)P.chunks * S1; i += BLOCK) {
+      const int c = (int)(i / S1), s = (int)(i % S1);
+      const int32_t h = P.hist[(size_t)c * P.nhist + hoff + s];
+      if (h) atomicAdd(&tot[s], h);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int64_t total = 0;
+      for (int s = 0; s < S1; s++) total += tot[s];
+      const int32_t keff = (int32_t)min((int64_t)P.q_kcap[q], total);
+      int32_t sstar = -1, need = 0, clt = 0, cum = 0;
+      if (keff > 0)
+        for (int s = 0; s < S1; s++) {
+          if (cum + tot[s] >= keff) { sstar = s; clt = cum; need = keff - cum; break; }
+          cum += tot[s];
+        }
+      s_sel[0] = keff; s_sel[1] = sstar; s_sel[2] = need; s_sel[3] = clt;
+      P.qsel[q * 4 + 0] = keff; P.qsel[q * 4 + 1] = sstar;
+      P.qsel[q * 4 + 2] = need; P.qsel[q * 4 + 3] = clt;
+      P.r_nroots[q] = keff;
+    }
+    __syncthreads();
+    const int32_t keff = s_sel[0], sstar = s_sel[1], need = s_sel[2];
+    if (keff > 0) {
+      int32_t carry = 0;
+      for (int base = 0; base < P.chunks; base += BLOCK) {
+        const int c = base + tid;
+        int32_t t = 0, lt = 0;
+        if (c < P.chunks) {
+          const int32_t *h = P.hist + (size_t)c * P.nhist + hoff;
+          t = h[sstar];
+          for (int s = 0; s < sstar; s++) lt += h[s];
+        }
+        int32_t btot;
+        const int32_t ex = block_scan(t, &btot) + carry;
+        carry += btot;
+        if (c < P.chunks && (lt > 0 || (t > 0 && ex < need))) {
+          const int32_t pos = atomicAdd(P.work_cnt, 1);
+          P.work[pos] = make_int4(q, c, ex, lt);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int lane_dist(const Pass &P, size_t idx, int bit) {
+  int d = 0;
+  for (int b = 0; b < P.B; b++) d |= (int)((P.planes[b * P.pstride + idx] >> bit) & 1ull) << b;
+  return d;
+}
+
+// ---- select: scan one chunk for one query in vertex order; keep every root
+// below s* and the first `need` ties overall (ranked across chunks).
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_select(const Pass P) {
+  const int tid = threadIdx.x;
+  const int n_items = *P.work_cnt;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int4 wk = P.work[it];
+    const int q = wk.x, c = wk.y, lt_c = wk.w;
+    const int32_t sstar = P.qsel[q * 4 + 1], need = P.qsel[q * 4 + 2];
+    const int word = P.q_word[q];
+    const uint64_t m = P.q_mask[q];
+    const size_t tb = (size_t)(word / T) * P.n * T;
+    const int w = word % T;
+    int32_t ties = wk.z, lts = 0;
+    const int64_t v0 = (int64_t)c * P.CH, v1 = min((int64_t)P.n, v0 + P.CH);
+    for (int64_t vb = v0; vb < v1; vb += BLOCK) {
+      const int64_t v = vb + tid;
+      bool lt = false, tie = false;
+      int s = 0;
+      if (v < v1) {
+        const size_t idx = tb + (size_t)v * T + w;
+        if ((P.vis[idx] & m) == m) {
+          for (int b = 0; b < P.B; b++) s += __popcll(P.planes[b * P.pstride + idx] & m) << b;
+          lt = s < sstar;
+          tie = s == sstar;
+        }
+      }
+      int32_t ntie, nlt;
+      const int32_t rank = block_scan(tie ? 1 : 0, &ntie) + ties;
+      block_scan(lt ? 1 : 0, &nlt);
+      if (lt || (tie && rank < need)) {
+        const int32_t pos = atomicAdd(&P.cand_cnt[q], 1);
+        P.cand[P.q_coff[q] + pos] = ((uint64_t)(uint32_t)s << 32) | (uint64_t)(uint32_t)v;
+      }
+      ties += ntie;
+      lts += nlt;
+      if (lts >= lt_c && ties >= need) break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- finish: order each query's candidates by (score, id); write roots,
+// scores and the per-keyword distances.
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_finish(const Pass P) {
+  constexpr int LDS_SORT = 2048;
+  __shared__ uint64_t s_key[LDS_SORT];
+  const int tid = threadIdx.x;
+  for (int q = blockIdx.x; q < P.nq; q += gridDim.x) {
+    const int32_t keff = P.qsel[q * 4 + 0];
+    if (keff == 0) continue;
+    uint64_t *g = P.cand + P.q_coff[q];
+    int N = 1;
+    while (N < keff) N <<= 1;
+    uint64_t *x = N <= LDS_SORT ? s_key : g;
+    for (int i = tid; i < N; i += BLOCK) x[i] = i < keff ? g[i] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= N; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < N; i += BLOCK) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const uint64_t a = x[i], b = x[ixj];
+            if ((a > b) == ((i & k) == 0)) { x[i] = b; x[ixj] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    const int word = P.q_word[q], w = word % T, nk = P.q_nk[q];
+    const size_t tb = (size_t)(word / T) * P.n * T;
+    const int roff = P.q_roff[q], kdoff = P.q_kdoff[q], boff = P.q_boff[q];
+    for (int i = tid; i < keff; i += BLOCK) {
+      const uint64_t key = x[i];
+      const int32_t v = (int32_t)(uint32_t)key;
+      P.r_roots[roff + i] = v;
+      P.r_scores[roff + i] = (int32_t)(key >> 32);
+      const size_t idx = tb + (size_t)v * T + w;
+      for (int j = 0; j < nk; j++) P.r_kwdist[kdoff + (size_t)i * nk + j] = (uint8_t)lane_dist(P, idx, P.bits[boff + j]);
+    }
+    __syncthreads();
+  }
+}
+
+// ---- answer: one wave per (query, root, keyword) walks from the root to
+// the smallest-id out-neighbour one hop closer, writing the path into the
+// keyword's segment of the root's edge slot; then one wave per (query, root)
+// merges the segments: sort, drop repeats.
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
+  constexpr int WAVES = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t waves = (int64_t)gridDim.x * WAVES;
+  for (int64_t item = (int64_t)blockIdx.x * WAVES + wid; item < P.total_kd; item += waves) {
+    int lo = 0, hi = P.nq;                      // query owning this (root, keyword) item
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (P.q_kdoff[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int q = lo, nk = P.q_nk[q];
+    const int rel = (int)(item - P.q_kdoff[q]), i = rel / nk, j = rel % nk;
+    if (i >= P.qsel[q * 4 + 0]) continue;
+    const int32_t r = P.r_roots[P.q_roff[q] + i];
+    int d = P.r_kwdist[item];
+    const int word = P.q_word[q], w = word % T, bit = P.bits[P.q_boff[q] + j];
+    const size_t tb = (size_t)(word / T) * P.n * T;
+    int2 *out = P.r_edges + P.q_eoff[q] + (size_t)i * P.q_ecap[q] + (size_t)j * P.q_dmax[q];
+    int32_t x = r;
+    int h = 0;
+    const int32_t sb = P.qk_seed_b[P.q_boff[q] + j];
+    const int64_t ns = P.qk_seed_e[P.q_boff[q] + j] - sb;
+    while (d > 0) {
+      int32_t best = 0x7fffffff;
+      const int32_t e0 = P.fwd_ptr[x], e1 = P.fwd_ptr[x + 1];
+      if (d == 1 && ns * 4 < (int64_t)(e1 - e0)) {
+        // last hop: the keyword's vertices are few compared with the row, so
+        // look each of them up in the sorted row and keep the smallest hit
+        const int32_t *seeds = P.inv_vtx + sb;
+        int32_t mine = 0x7fffffff;
+        for (int64_t k = lane; k < ns; k += 64) {
+          const int32_t v = seeds[k];
+          int32_t lo = e0, hi = e1;
+          while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (P.fwd_col[mid] < v) lo = mid + 1; else hi = mid;
+          }
+          if (lo < e1 && P.fwd_col[lo] == v) mine = min(mine, v);
+        }
+        for (int off = 32; off > 0; off >>= 1) mine = min(mine, __shfl_xor(mine, off));
+        best = mine;
+      } else {
+        // rows are sorted by neighbour id, so the first qualifying neighbour
+        // in row order is the smallest-id one; four chunks of 64 per round
+        constexpr int U = 4;
+        for (int32_t eb = e0; eb < e1 && best == 0x7fffffff; eb += 64 * U) {
+          int32_t y[U];
+          bool ok[U];
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            const int32_t e = eb + u * 64 + lane;
+            y[u] = e < e1 ? P.fwd_col[e] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < U; u++)
+            ok[u] = y[u] >= 0 && ((P.vis[tb + (size_t)y[u] * T + w] >> bit) & 1ull);
+#pragma unroll
+          for (int u = 0; u < U; u++)
+            if (ok[u]) ok[u] = lane_dist(P, tb + (size_t)y[u] * T + w, bit) == d - 1;
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            const uint64_t bal = __ballot(ok[u]);
+            if (bal && best == 0x7fffffff) best = __shfl(y[u], __ffsll((long long)bal) - 1);
+          }
+        }
+      }
+      if (best == 0x7fffffff || h >= P.q_dmax[q]) break;   // cannot happen for a BFS-consistent state
+      if (lane == 0) out[h] = make_int2(x, best);
+      h++;
+      x = best;
+      d--;
+    }
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_answer_merge(const Pass P) {
+  constexpr int WAVES = BLOCK / 64, ECAP = KWS_MAX_KW * KWS_MAX_DMAX;
+  __shared__ uint64_t s_e[WAVES][ECAP];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint64_t *eb = s_e[wid];
+  const int64_t waves = (int64_t)gridDim.x * WAVES;
+  for (int64_t slot = (int64_t)blockIdx.x * WAVES + wid; slot < P.total_slots; slot += waves) {
+    if (lane != 0) continue;
+    int lo = 0, hi = P.nq;                      // query owning this slot
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (P.q_roff[mid] <= slot) lo = mid; else hi = mid;
+    }
+    const int q = lo, i = (int)(slot - P.q_roff[q]);
+    if (i >= P.qsel[q * 4 + 0]) continue;
+    const int nk = P.q_nk[q], dm = P.q_dmax[q];
+    int2 *seg = P.r_edges + P.q_eoff[q] + (size_t)i * P.q_ecap[q];
+    const uint8_t *kd = P.r_kwdist + P.q_kdoff[q] + (size_t)i * nk;
+    int ne = 0;
+    for (int j = 0; j < nk; j++)
+      for (int h = 0; h < kd[j] && h < dm; h++) {
+        const int2 e = seg[j * dm + h];
+        eb[ne++] = ((uint64_t)(uint32_t)e.x << 32) | (uint32_t)e.y;
+      }
+    for (int a = 1; a < ne; a++) {             // insertion sort, then drop repeats
+      const uint64_t key = eb[a];
+      int b = a - 1;
+      while (b >= 0 && eb[b] > key) { eb[b + 1] = eb[b]; b--; }
+      eb[b + 1] = key;
+    }
+    int u = 0;
+    for (int a = 0; a < ne; a++) {
+      if (a > 0 && eb[a] == eb[a - 1]) continue;
+      seg[u++] = make_int2((int32_t)(eb[a] >> 32), (int32_t)(uint32_t)eb[a]);
+    }
+    P.r_ecount[slot] = u;
+  }
+}
+
+// ---- export one lane's distances (verification entry point)
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_export(const Pass P, uint8_t *out) {
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < P.n; v += (int64_t)gridDim.x * BLOCK) {
+    const size_t idx = (size_t)v * T;
+    out[v] = (P.vis[idx] & 1ull) ? (uint8_t)lane_dist(P, idx, 0) : (uint8_t)KWS_DIST_INF;
+  }
+}
+
+
+// ============================================================ launchers
+
+namespace {
+
+inline unsigned clamp_grid(int64_t blocks) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 1 << 16));
+}
+
+kws_status launch_check(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(KWS_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return KWS_OK;
+}
+
+struct Timer {
+  Profiler &p;
+  hipStream_t s;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timer(Profiler &p_, hipStream_t s_, int c) : p(p_), s(s_), cls(c) { p.begin(cls, s, &a); }
+  ~Timer() { p.end(cls, s, a); }
+};
+
+__global__ void k_fill_u64(uint64_t *p, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < count; i += (size_t)gridDim.x * BLOCK) p[i] = 0;
+}
+
+template <int T>
+kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
+  const int Wq = std::min(64, P.Wp < 2 ? 1 : 1 << (32 - __builtin_clz((unsigned)P.Wp - 1)));
+  {
+    Timer t(prof, s, KC_PUSH);
+    k_push<T><<<2048, BLOCK, 0, s>>>(P, S, Wq);
+  }
+  KWS_TRY(launch_check("push"));
+  constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
+  PullGrid pg;
+  const int sizes[BIN_COUNT + 1] = {S_SMALL, S_MED, 64, 64};
+  pg.boff[0] = 0;
+  for (int b = 0; b <= BIN_COUNT; b++) {
+    const int64_t items = b < BIN_COUNT ? P.bin_begin[b + 1] - P.bin_begin[b] : P.n_hub;
+    const int64_t gpb = BLOCK / sizes[b];
+    const int64_t bpt = items ? std::min<int64_t>((items + gpb - 1) / gpb, 16384 / P.tiles + 1) : 0;
+    pg.boff[b + 1] = pg.boff[b] + (int32_t)(bpt * P.tiles);
+  }
+  {
+    Timer t(prof, s, KC_PULL);
+    k_pull<T><<<(unsigned)std::max(1, pg.boff[BIN_COUNT + 1]), BLOCK, 0, s>>>(P, S, pg);
+  }
+  return launch_check("pull");
+}
+
+template <int T>
+kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
+  const unsigned grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + FIN_CHUNK - 1) / FIN_CHUNK, 8192));
+  {
+    Timer t(prof, s, KC_FINALIZE);
+    k_finalize<T><<<grid, BLOCK, sizeof(uint64_t) * (size_t)P.Wp, s>>>(P, S);
+  }
+  return launch_check("finalize");
+}
+
+template <int T>
+kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
+  if (P.nq == 0) return KWS_OK;
+  {
+    Timer t(prof, s, KC_SCORE);
+    const size_t lds = (P.te_lds ? sizeof(uint64_t) * P.nq : 0) + (P.hist_lds ? sizeof(int32_t) * P.nhist : 0);
+    const int64_t split = (P.CH + BLOCK * SC_R - 1) / (BLOCK * SC_R);
+    k_score<T><<<clamp_grid(P.chunks * split), BLOCK, lds, s>>>(P);
+  }
+  KWS_TRY(launch_check("score"));
+  {
+    Timer t(prof, s, KC_THRESHOLD);
+    k_threshold<<<clamp_grid(P.nq), BLOCK, 0, s>>>(P);
+  }
+  KWS_TRY(launch_check("threshold"));
+  {
+    Timer t(prof, s, KC_SELECT);
+    k_select<T><<<2048, BLOCK, 0, s>>>(P);
+  }
+  KWS_TRY(launch_check("select"));
+  {
+    Timer t(prof, s, KC_FINISH);
+    k_finish<T><<<clamp_grid(P.nq), BLOCK, 0, s>>>(P);
+  }
+  KWS_TRY(launch_check("finish"));
+  {
+    Timer t(prof, s, KC_ANSWER);
+    const int64_t waves = BLOCK / 64;
+    k_answer<T><<<clamp_grid((P.total_kd + waves - 1) / waves), BLOCK, 0, s>>>(P);
+    k_answer_merge<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
+  }
+  return launch_check("answer");
+}
+
+#define KWS_DISPATCH_T(T_, CALL)                                   \
+  switch (T_) {                                                     \
+    case 1: { constexpr int TT = 1; return CALL; }                  \
+    case 2: { constexpr int TT = 2; return CALL; }                  \
+    case 4: { constexpr int TT = 4; return CALL; }                  \
+    case 8: { constexpr int TT = 8; return CALL; }                  \
+    case 16: { constexpr int TT = 16; return CALL; }                \
+  }                                                                 \
+  return fail(KWS_EINVAL, "tile width %d not supported", T_);
+
+}  // namespace
+
+kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
+  const int64_t items =
+      std::max<int64_t>(P.total_seeds, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
+  {
+    Timer t(prof, s, KC_SEED);
+    switch (P.T) {
+      case 1: k_seed<1><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
+      case 2: k_seed<2><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
+      case 4: k_seed<4><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
+      case 8: k_seed<8><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
+      case 16: k_seed<16><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
+      default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
+    }
+  }
+  return launch_check("seed");
+}
+
+kws_status launch_expand(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
+  KWS_DISPATCH_T(P.T, expand_t<TT>(P, S, s, prof))
+}
+
+kws_status launch_finalize(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
+  KWS_DISPATCH_T(P.T, finalize_t<TT>(P, S, s, prof))
+}
+
+kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof) {
+  KWS_DISPATCH_T(P.T, finish_t<TT>(P, s, prof))
+}
+
+kws_status launch_export(const Pass &P, uint8_t *out, hipStream_t s) {
+  if (P.T != 1) return fail(KWS_EINVAL, "distance export needs a one-word pass");
+  k_export<1><<<clamp_grid(((int64_t)P.n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P, out);
+  return launch_check("export");
+}
+
+kws_status launch_fill_zero(uint64_t *p, size_t words, hipStream_t s) {
+  if (words == 0) return KWS_OK;
+  k_fill_u64<<<clamp_grid((int64_t)((words + BLOCK - 1) / BLOCK)), BLOCK, 0, s>>>(p, words);
+  return launch_check("fill");
+}
+
+}  // namespace kws

@@ -1,0 +1,88 @@
+// Device-side descriptors of one device pass and of one BFS step, and the
+// launchers of the kernels that work on them (internal).
+//
+// Lanes. Every (query, keyword) needs one BFS. A lane is one bit of a 64-bit
+// mask word; all lanes of a query sit in one word, and queries packed into
+// the same word share a lane when they ask for the same keyword with the
+// same d_max. Per vertex and word the device keeps:
+//   vis    lanes whose BFS has reached the vertex (dist <= current level)
+//   fr     lanes that reached it exactly at the current level (two buffers)
+//   nxt    lanes arriving at the next level (push target; zero between steps)
+//   P_b    bit b of the distance of each reached lane (bit-sliced distances)
+// Layout [tile][vertex][T words]: the T words of one vertex are contiguous,
+// so one neighbour visit gathers 8*T bytes; a tile is one contiguous slab.
+#pragma once
+
+#include "kws_internal.h"
+
+namespace kws {
+
+struct Pass {
+  // sizes
+  int32_t n, T, tiles, Wp, B, nq, n_lanes;
+  int32_t chunks, CH, nhist, hist_lds, te_lds;
+  int32_t force_dir;
+  float alpha;
+  int64_t total_seeds, n_hub, total_slots, total_kd;
+  int64_t bin_begin[BIN_COUNT + 1];
+  size_t pstride;                    // words per plane = tiles * n * T
+  // graph
+  const int32_t *fwd_ptr, *fwd_col, *rev_ptr, *rev_col, *inv_vtx;
+  const int32_t *bin_vtx, *hub_v, *hub_b, *hub_e;
+  // state
+  uint64_t *vis, *fr0, *fr1, *nxt, *planes;
+  int32_t *flist, *flist_eoff;
+  // lanes to seed
+  const int64_t *lane_seed_off;      // [n_lanes + 1]
+  const int32_t *lane_seed_begin;    // [n_lanes]
+  const int32_t *lane_word, *lane_bit;
+  // queries to finish (score, rank, answer)
+  const int32_t *word_q_ptr, *word_q;
+  const uint64_t *q_mask;
+  const int32_t *q_word, *q_dmax, *q_nk, *q_kcap, *q_hoff, *q_coff, *q_ccap, *q_roff, *q_kdoff,
+      *q_eoff, *q_ecap, *q_boff;
+  const uint8_t *bits;               // lane bit of each query keyword, keyword order
+  const int32_t *qk_seed_b, *qk_seed_e;   // inverted-index slice of each query keyword
+  // zeroed by the seed kernel
+  uint64_t *zero0; int64_t zero0_words;
+  uint64_t *zero1; int64_t zero1_words;
+  uint64_t *zero2; int64_t zero2_words;
+  uint64_t *te;                      // [nq]
+  int32_t *cand_cnt, *work_cnt, *hist;
+  // scratch
+  int32_t *qsel;                     // [nq * 4]: k_eff, s*, need, c_lt
+  int4 *work;
+  uint64_t *cand;
+  // results
+  int32_t *r_nroots, *r_roots, *r_scores, *r_ecount;
+  uint8_t *r_kwdist;
+  int2 *r_edges;
+};
+
+// One BFS step over all words: expand the current frontier (lanes in
+// act_exp) and finalize the arrivals. Per word, newlvl is the distance the
+// arrivals get; 0 means the word starts here (vis is reset to the seeds and
+// the distance planes are cleared).
+struct Step {
+  const uint64_t *act_exp;   // [Wp] lanes that expand in this step
+  const uint64_t *live_in;   // [Wp] lanes whose current frontier is non-empty
+  const uint64_t *st_in;     // statistics of the current frontier (direction choice)
+  const uint64_t *fr_cur;
+  uint64_t *fr_next;
+  const uint64_t *act_new;   // [Wp] lanes allowed to gain a distance in this step
+  const uint64_t *act_nn;    // [Wp] lanes that would expand in the following step
+  const int8_t *newlvl;      // [Wp]
+  uint64_t *st_out;          // statistics of the new frontier: (n_f << 32 | m_f), m_u
+  uint64_t *live_out;        // [Wp]
+  int32_t build_list;        // write the frontier list (a following push reads it)
+  int32_t write_next;        // write fr_next and live_out
+};
+
+kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof);
+kws_status launch_expand(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
+kws_status launch_finalize(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
+kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof);
+kws_status launch_export(const Pass &P, uint8_t *out, hipStream_t s);
+kws_status launch_fill_zero(uint64_t *p, size_t words, hipStream_t s);
+
+}  // namespace kws

@@ -62,6 +62,11 @@ class Options(C.Structure):
                 ("block", C.c_int32), ("use_graph", C.c_int32), ("share_lanes", C.c_int32)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("configs_tried", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double),
+                ("from_cache", C.c_int32)]
+
+
 class GraphInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int64), ("n_labels", C.c_int32), ("hierarchical", C.c_int32),
                 ("device_bytes", C.c_int64), ("max_out_degree", C.c_int32), ("max_in_degree", C.c_int32)]
@@ -82,6 +87,22 @@ class BatchStats(C.Structure):
                     levels=L, passes=self.passes, pulled=list(self.pulled[:L]),
                     frontier=list(self.frontier[:L + 1]), frontier_edges=list(self.frontier_edges[:L + 1]),
                     unfinished_edges=list(self.unfinished_edges[:L + 1]))
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("max_words", C.c_int32), ("max_dmax", C.c_int32), ("queue_capacity", C.c_int32),
+                ("tile_words", C.c_int32), ("mem_bytes", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("rejected", C.c_int64), ("steps", C.c_int64), ("queued", C.c_int32),
+                ("active_words", C.c_int32), ("max_words", C.c_int32), ("elapsed_s", C.c_double),
+                ("qps", C.c_double), ("p50_us", C.c_double), ("p99_us", C.c_double),
+                ("mean_active_words", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -121,6 +142,15 @@ def load_library(path: str = LIB_PATH):
         "kws_profile_name": (C.c_char_p, [C.c_int32]),
         "kws_last_batch_stats": (C.c_int, [P, C.POINTER(BatchStats)]),
         "kws_last_error": (C.c_char_p, []),
+        "kws_autotune": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.c_int32, C.c_double, C.c_char_p,
+                                   C.POINTER(Options), C.POINTER(TuneReport)]),
+        "kws_server_create": (C.c_int, [P, C.POINTER(ServerOpts), C.POINTER(P)]),
+        "kws_server_submit": (C.c_int, [P, C.POINTER(QueryC), C.POINTER(C.c_uint64)]),
+        "kws_server_poll": (C.c_int, [P, C.c_uint64, C.POINTER(ResultC), C.POINTER(C.c_int32)]),
+        "kws_server_wait": (C.c_int, [P, C.c_uint64, C.c_int64, C.POINTER(ResultC), C.POINTER(C.c_int32)]),
+        "kws_server_cancel": (C.c_int, [P, C.c_uint64]),
+        "kws_server_stats_get": (C.c_int, [P, C.POINTER(ServerStats)]),
+        "kws_server_destroy": (None, [P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -302,6 +332,14 @@ class Graph:
         o = Options(direction, alpha, tile_words, 0, use_graph, share_lanes)
         _check(self._lib.kws_set_options(self.h, C.byref(o)))
 
+    def autotune(self, queries, reps: int = 3, budget_ms: float = 0.0, cache_path: Optional[str] = None):
+        """Time the sample batch under a grid of options, keep the fastest (see kws_autotune)."""
+        qa, keep = _queries(queries)
+        o, rep = Options(), TuneReport()
+        _check(self._lib.kws_autotune(self.h, qa, len(queries), reps, budget_ms,
+                                      cache_path.encode() if cache_path else None, C.byref(o), C.byref(rep)))
+        return ({k: getattr(o, k) for k, _ in o._fields_}, {k: getattr(rep, k) for k, _ in rep._fields_})
+
     def get_options(self) -> Options:
         o = Options()
         _check(self._lib.kws_get_options(self.h, C.byref(o)))
@@ -341,6 +379,62 @@ class Graph:
         s = BatchStats()
         _check(self._lib.kws_last_batch_stats(self.h, C.byref(s)))
         return s
+
+
+class Server:
+    """Continuous-batching server over a resident Graph (wraps kws_server)."""
+
+    def __init__(self, graph: Graph, max_words: int = 0, max_dmax: int = 0, queue_capacity: int = 0,
+                 tile_words: int = 0, mem_bytes: int = 0):
+        self._lib = load_library()
+        self.graph = graph
+        o = ServerOpts(max_words, max_dmax, queue_capacity, tile_words, mem_bytes)
+        h = C.c_void_p()
+        _check(self._lib.kws_server_create(graph.h, C.byref(o), C.byref(h)))
+        self.h = h
+
+    def submit(self, kw, d_max: int, k: int) -> int:
+        qa, keep = _queries([(kw, d_max, k)])
+        t = C.c_uint64()
+        _check(self._lib.kws_server_submit(self.h, qa, C.byref(t)))
+        return int(t.value)
+
+    def _finish(self, st, r, done):
+        _check(st)
+        if not done.value:
+            return None
+        try:
+            return _take(r)
+        finally:
+            self._lib.kws_result_free(C.byref(r))
+
+    def poll(self, ticket: int) -> Optional[Result]:
+        r, done = ResultC(), C.c_int32()
+        return self._finish(self._lib.kws_server_poll(self.h, ticket, C.byref(r), C.byref(done)), r, done)
+
+    def wait(self, ticket: int, timeout_s: Optional[float] = None) -> Optional[Result]:
+        r, done = ResultC(), C.c_int32()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        return self._finish(self._lib.kws_server_wait(self.h, ticket, us, C.byref(r), C.byref(done)), r, done)
+
+    def cancel(self, ticket: int):
+        _check(self._lib.kws_server_cancel(self.h, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.kws_server_stats_get(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.kws_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _torch_hooks = None

@@ -93,3 +93,15 @@ def test_product_path_has_no_cpu_fallback():
             B.load_library("/nonexistent/libkws.so")
         finally:
             B._lib = saved
+
+
+def test_server_null_arguments():
+    lib = K.load_library()
+    t = C.c_uint64()
+    assert lib.kws_server_create(None, None, None) == K.EINVAL
+    assert lib.kws_server_submit(None, None, C.byref(t)) == K.EINVAL
+    r, d = B.ResultC(), C.c_int32()
+    assert lib.kws_server_poll(None, 1, C.byref(r), C.byref(d)) == K.EINVAL
+    assert lib.kws_server_cancel(None, 1) == K.EINVAL
+    lib.kws_server_destroy(None)
+    lib.kws_batch_result_free(None)

@@ -1,0 +1,134 @@
+"""GPU tests of the serving loop and of the captured-graph batch path.
+
+* every served result equals the oracle's, whether the query ran alone or
+  arrived while others were on the device (continuous batching);
+* queries with different radii and keyword counts share slots and steps;
+* cancel, queue-full (EBUSY) and shutdown with work in flight;
+* the hipGraph replay of a batch gives the same answers as direct launches.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import assert_all_same, assert_same, oracle_results
+from synth import gen, tiny, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def K():
+    import paper_2504_09311_amd as K
+    K.load_library()
+    return K
+
+
+@pytest.fixture(scope="module")
+def rmat14(K):
+    g = workloads.rmat_flat(14)
+    return g, oracle.Oracle(g), K.Graph.from_synth(g)
+
+
+def test_served_alone_equals_mix_equals_oracle(K, rmat14):
+    g, o, G = rmat14
+    qs = workloads.rmat_flat_queries(120, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=3)
+    want = oracle_results(o, qs)
+    S = K.Server(G, max_words=6, max_dmax=4, tile_words=2)
+    say("served alone")
+    alone = []
+    for q in qs[:20]:
+        t = S.submit(q.kw, q.d_max, q.k)
+        alone.append(S.wait(t, 30.0))
+    assert_all_same(alone, want[:20], "alone")
+    say("served mix")
+    tickets = []
+    for i, q in enumerate(qs):
+        tickets.append(S.submit(q.kw, q.d_max, q.k))
+        if i % 7 == 0:
+            time.sleep(0.0005)      # arrivals spread while earlier queries run
+    mix = [S.wait(t, 60.0) for t in tickets]
+    assert all(r is not None for r in mix)
+    assert_all_same(mix, want, "mix")
+    st = S.stats()
+    assert st["completed"] == 140 and st["steps"] > 0 and st["p99_us"] >= st["p50_us"] > 0
+    assert st["mean_active_words"] > 1.0          # slots really overlapped on the device
+    S.close()
+
+
+def test_served_tiny_graphs(K):
+    for seed in range(0, 40):
+        g = tiny.random_graph(seed)
+        qs = [q for q in tiny.random_queries(g, seed, 8)]
+        o = oracle.Oracle(g)
+        want = [o.search(q.kw, q.d_max, q.k) for q in qs]
+        G = K.Graph.from_synth(g)
+        S = K.Server(G, max_words=3, tile_words=1)
+        ts = [S.submit(q.kw, q.d_max, q.k) for q in qs]
+        got = [S.wait(t, 30.0) for t in ts]
+        assert_all_same(got, want, f"served tiny {seed}")
+        S.close()
+        G.close()
+
+
+def test_server_cancel_busy_and_shutdown(K, rmat14):
+    g, o, G = rmat14
+    qs = workloads.rmat_flat_queries(40, 2, 6, [3], 10, cfg=2, qcfg=7)
+    S = K.Server(G, max_words=1, queue_capacity=8, max_dmax=3)
+    tickets, busy = [], 0
+    for q in qs:
+        try:
+            tickets.append(S.submit(q.kw, q.d_max, q.k))
+        except K.KwsError as e:
+            assert e.status == K.EBUSY
+            busy += 1
+    assert busy > 0
+    S.cancel(tickets[-1])
+    with pytest.raises(K.KwsError) as e:
+        S.wait(tickets[-1], 30.0)
+    assert e.value.status == K.ECANCELLED
+    first = S.wait(tickets[0], 30.0)
+    assert_same(first, o.search(qs[0].kw, qs[0].d_max, qs[0].k), "first served")
+    with pytest.raises(K.KwsError) as e:
+        S.poll(123456789)
+    assert e.value.status == K.EINVAL
+    with pytest.raises(K.KwsError):
+        S.submit([1], 4, 5)                       # above the server's max_dmax
+    S.close()                                    # queued work cancelled, running slot drained
+    # the graph is still usable afterwards
+    r = G.keyword_search(qs[1].kw, qs[1].d_max, qs[1].k)
+    assert_same(r, o.search(qs[1].kw, qs[1].d_max, qs[1].k), "after shutdown")
+
+
+def test_graph_replay_matches(K, rmat14):
+    g, o, G = rmat14
+    qs = workloads.rmat_flat_queries(64, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=5)
+    want = oracle_results(o, qs)
+    G.set_options(use_graph=1)
+    for rep in range(3):
+        say("graph replay", rep)
+        assert_all_same(G.search_batch(qs), want, f"graph replay {rep}")
+        # the program's own eager work between replays
+        r = G.keyword_search(qs[rep].kw, qs[rep].d_max, qs[rep].k)
+        assert_same(r, want[rep], "eager between replays")
+    G.set_options()
+
+
+def test_autotune_picks_identical_answers_and_caches(K, rmat14, tmp_path):
+    g, o, G = rmat14
+    qs = workloads.rmat_flat_queries(48, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=9)
+    want = oracle_results(o, qs)
+    cache = str(tmp_path / "tune.txt")
+    best, rep = G.autotune(qs, reps=2, cache_path=cache)
+    assert rep["configs_tried"] > 10 and rep["best_ms"] <= rep["default_ms"] and not rep["from_cache"]
+    assert_all_same(G.search_batch(qs), want, "tuned")
+    best2, rep2 = G.autotune(qs, reps=2, cache_path=cache)
+    assert rep2["from_cache"] and best2["tile_words"] == best["tile_words"]
+    G.set_options()
