@@ -103,7 +103,8 @@ typedef struct {
  *      of roots[i] are entries edge_ptr[i] .. edge_ptr[i+1]-1, sorted (src,dst).
  *  te                 reverse edges a plain per-keyword BFS would scan for
  *                     this query (in-degrees of vertices at dist < d_max,
- *                     summed over keywords): the GTEPS numerator. */
+ *                     summed over keywords): the GTEPS numerator; -1 unless
+ *                     the count_te option is on. */
 typedef struct {
   int32_t n_roots;
   int32_t n_kw;
@@ -166,6 +167,8 @@ typedef struct {
   int32_t block;         /* threads per workgroup for the streaming kernels: 64..1024 */
   int32_t use_graph;     /* 1: capture each batch shape once in a hipGraph and replay it */
   int32_t share_lanes;   /* 1 (default): queries in one word share equal (keyword, d_max) lanes; -1: off */
+  int32_t count_te;      /* 1: fill kws_result.te (costs a reduction per query in the score step);
+                            0 (default): te = -1 */
 } kws_options;
 kws_status kws_set_options(kws_graph *g, const kws_options *opt);
 kws_status kws_get_options(kws_graph *g, kws_options *opt);

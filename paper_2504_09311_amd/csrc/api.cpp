@@ -119,7 +119,7 @@ void HostBuf::release() {
 }
 
 void Engine::release() {
-  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &plan, &zero_region,
+  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags, &plan, &zero_region,
                  &qsel, &work, &cand, &arena};
   for (DevBuf *b : d) b->release();
   h_plan.release();
@@ -315,6 +315,7 @@ kws_status kws_set_options(kws_graph *g, const kws_options *opt) {
   if (opt->block && opt->block != kws::BLOCK) return kws::fail(KWS_EINVAL, "block must be %d", kws::BLOCK);
   o.use_graph = opt->use_graph > 0 ? 1 : 0;
   o.share_lanes = opt->share_lanes < 0 ? -1 : 1;
+  o.count_te = opt->count_te > 0 ? 1 : 0;
   std::lock_guard<std::mutex> lk(g->mu);
   g->opt = o;
   return KWS_OK;

@@ -91,6 +91,8 @@ extern "C" kws_status kws_autotune(kws_graph *g, const kws_query *qs, int32_t nq
   if (kws::cache_lookup(cache_path, key, &choice)) {
     g->opt = choice;
     g->opt.use_graph = saved.use_graph;
+    g->opt.count_te = saved.count_te;
+    g->opt.share_lanes = saved.share_lanes;
     rep.from_cache = 1;
     if (best) *best = g->opt;
     if (report) *report = rep;
@@ -99,6 +101,8 @@ extern "C" kws_status kws_autotune(kws_graph *g, const kws_query *qs, int32_t nq
   std::vector<kws_options> grid;
   kws_options d;
   kws::default_options(&d);
+  d.count_te = saved.count_te;       // what the caller asked the answers to contain stays as it was
+  d.share_lanes = saved.share_lanes;
   grid.push_back(d);
   for (int tw : {1, 2, 4, 8, 16})
     for (int pol = 0; pol < 6; pol++) {
@@ -142,6 +146,8 @@ extern "C" kws_status kws_autotune(kws_graph *g, const kws_query *qs, int32_t nq
     return st;
   }
   best_o.use_graph = saved.use_graph;
+  best_o.count_te = saved.count_te;
+  best_o.share_lanes = saved.share_lanes;
   g->opt = best_o;
   rep.best_ms = best_ms;
   kws::cache_store(cache_path, key, best_o, best_ms);

@@ -95,7 +95,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
 
 // Turns the copied-back arena into results for the pass's queries.
 kws_status collect_results(const QueryTables &Q, const std::vector<const QIn *> &qs, const uint8_t *ha,
-                           const ArenaLayout &al, kws_result *const *out, FlatOut *flat);
+                           const ArenaLayout &al, bool te_counted, kws_result *const *out, FlatOut *flat);
 
 // Per-vertex search state of `words_per_array` words (nxt starts at zero).
 kws_status ensure_state(Engine &E, size_t words_per_array, hipStream_t s);

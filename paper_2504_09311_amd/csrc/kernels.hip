@@ -12,12 +12,32 @@
 
 namespace kws {
 
-__device__ __forceinline__ int pick_dir(const uint64_t *st, float alpha, int force) {
-  const uint64_t packed = st[0];
+// Frontier statistics are spread over STAT_STRIPES cache lines (one stripe
+// per group of blocks) so that no single address takes every block's atomic.
+__device__ __forceinline__ uint64_t *stat_stripe(uint64_t *st, int64_t block) {
+  return st + (size_t)(block % STAT_STRIPES) * STAT_STRIDE;
+}
+
+// Sums the stripes once per block (every thread of the block must call it)
+// and returns 0 (nothing to expand), 1 (push) or 2 (pull).
+__device__ int pick_dir(const uint64_t *st, float alpha, int force, uint32_t *nf_out = nullptr,
+                        uint32_t *mf_out = nullptr) {
+  __shared__ uint64_t s_tot[2];
+  const int tid = threadIdx.x;
+  uint64_t a = 0, b = 0;
+  if (tid < STAT_STRIPES) { a = st[(size_t)tid * STAT_STRIDE]; b = st[(size_t)tid * STAT_STRIDE + 1]; }
+  if (tid < 64)
+    for (int off = 32; off > 0; off >>= 1) { a += __shfl_xor(a, off); b += __shfl_xor(b, off); }
+  if (tid == 0) { s_tot[0] = a; s_tot[1] = b; }
+  __syncthreads();
+  const uint64_t packed = s_tot[0], mu = s_tot[1];
+  __syncthreads();
   const uint32_t nf = (uint32_t)(packed >> 32), mf = (uint32_t)packed;
+  if (nf_out) *nf_out = nf;
+  if (mf_out) *mf_out = mf;
   if (nf == 0) return 0;                       // empty frontier: nothing to expand
   if (force == 1 || force == 2) return force;
-  return (double)alpha * (double)mf > (double)st[1] ? 2 : 1;   // 1 push, 2 pull
+  return (double)alpha * (double)mf > (double)mu ? 2 : 1;   // 1 push, 2 pull
 }
 
 __device__ __forceinline__ uint64_t group_bits(int lane, int S) {
@@ -56,12 +76,22 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
   for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
   for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
   for (int64_t i = gid; i < P.zero2_words; i += gsz) P.zero2[i] = 0;
-  for (int64_t i = gid; i < P.total_seeds; i += gsz) {
-    int lo = 0, hi = P.n_lanes;               // largest lane with lane_seed_off[lane] <= i
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (P.lane_seed_off[mid] <= i) lo = mid; else hi = mid;
+  __shared__ int s_lane;
+  for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < P.total_seeds; base += gsz) {
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = P.n_lanes;             // largest lane with lane_seed_off[lane] <= base
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P.lane_seed_off[mid] <= base) lo = mid; else hi = mid;
+      }
+      s_lane = lo;
     }
+    __syncthreads();
+    int lo = s_lane;
+    __syncthreads();
+    const int64_t i = base + threadIdx.x;
+    if (i >= P.total_seeds) continue;
+    while (lo + 1 < P.n_lanes && P.lane_seed_off[lo + 1] <= i) lo++;
     const int32_t v = P.inv_vtx[P.lane_seed_begin[lo] + (int32_t)(i - P.lane_seed_off[lo])];
     const int word = P.lane_word[lo];
     const size_t idx = ((size_t)(word / T) * P.n + v) * T + (word % T);
@@ -69,114 +99,140 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
   }
 }
 
-// ---- finalize one step: new = nxt & ~vis & act_new; vis |= new; distance planes; next frontier
-// buffer; nxt cleared; the statistics that pick the direction of the next
-// level. Frontier vertices are compacted into LDS per chunk of FIN_CHUNK
-// vertices (wavefront ballot + prefix sums), then one atomic per chunk
-// reserves their place in the global list and its in-edge offsets.
-constexpr int FIN_CHUNK = 512;
-
+// ---- finalize one step: new = nxt & ~vis & act_new; vis |= new; distance
+// planes; next frontier buffer; nxt cleared; a frontier flag per vertex;
+// the statistics that pick the direction of the next level (frontier size,
+// its in-edges, out-edges of vertices still missing lanes), accumulated in
+// registers and reduced once per wavefront. A pure streaming pass: the
+// frontier list a push needs is built by k_compact, only for levels that push.
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) {
   extern __shared__ uint64_t s_live[];                    // [Wp]
-  __shared__ int32_t s_lv[FIN_CHUNK], s_le[FIN_CHUNK];
-  __shared__ int32_t s_wcnt[BLOCK / 64], s_wedge[BLOCK / 64];
-  __shared__ int32_t s_cnt, s_edges;
-  __shared__ uint64_t s_base;
   constexpr int G = T, VPB = BLOCK / T;   // T threads per vertex, one per word of a tile
-  const int tid = threadIdx.x, gl = tid & (G - 1), lane = tid & 63, wid = tid >> 6;
+  constexpr int TG = 8;                   // tiles whose words are loaded before any store
+  const int tid = threadIdx.x, gl = tid & (G - 1), lane = tid & 63;
   const uint64_t gmask = group_bits(lane, G);
-  uint64_t *st = S.st_out;
   for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
-  uint64_t mu_acc = 0;
-  const int64_t nchunks = ((int64_t)P.n + FIN_CHUNK - 1) / FIN_CHUNK;
-  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    if (tid == 0) { s_cnt = 0; s_edges = 0; }
-    __syncthreads();
-    const int64_t c0 = c * FIN_CHUNK, c1 = min((int64_t)P.n, c0 + FIN_CHUNK);
-    for (int64_t vb = c0; vb < c1; vb += VPB) {
-      const int64_t v = vb + tid / G;
-      const bool valid = v < c1;
-      uint64_t anyf = 0, anyneed = 0;
-      if (valid) {
-        constexpr int TG = 8;   // tiles whose words are loaded before any store
-        for (int t0 = 0; t0 < P.tiles; t0 += TG) {
-          uint64_t nxv[TG], oldv[TG];
+  __syncthreads();
+  uint64_t live_acc[TG] = {0, 0, 0, 0, 0, 0, 0, 0};   // lanes with new frontier, first TG tiles
+  uint64_t nf_acc = 0, mf_acc = 0, mu_acc = 0;
+  for (int64_t vb = (int64_t)blockIdx.x * VPB; vb < P.n; vb += (int64_t)gridDim.x * VPB) {
+    const int64_t v = vb + tid / G;
+    const bool valid = v < P.n;
+    uint64_t anyf = 0, anyneed = 0;
+    if (valid) {
+      for (int t0 = 0; t0 < P.tiles; t0 += TG) {
+        uint64_t nxv[TG], oldv[TG];
 #pragma unroll
-          for (int k = 0; k < TG; k++) {
-            const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
-            nxv[k] = t0 + k < P.tiles ? P.nxt[idx] : 0ull;
-            oldv[k] = t0 + k < P.tiles ? P.vis[idx] : 0ull;
-          }
+        for (int k = 0; k < TG; k++) {
+          const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
+          nxv[k] = t0 + k < P.tiles ? P.nxt[idx] : 0ull;
+          oldv[k] = t0 + k < P.tiles ? P.vis[idx] : 0ull;
+        }
 #pragma unroll
-          for (int k = 0; k < TG; k++) {
-            if (t0 + k >= P.tiles) break;
-            const int j = (t0 + k) * T + gl;
-            const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
-            const uint64_t nx = nxv[k];
-            const int nl = S.newlvl[j];
-            const uint64_t old = nl ? oldv[k] : 0ull;
-            const uint64_t fnew = nx & ~old & S.act_new[j];
-            const uint64_t nv = old | fnew;
-            if (nl == 0) {
-              P.vis[idx] = nv;
-              for (int b = 0; b < P.B; b++) P.planes[b * P.pstride + idx] = 0;
-            } else if (fnew) {
-              P.vis[idx] = nv;
-              for (int b = 0; b < P.B; b++)
-                if ((nl >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
-            }
-            if (S.write_next) {
-              S.fr_next[idx] = fnew;
-              if (fnew) atomicOr((unsigned long long *)&s_live[j], fnew);
-              anyneed |= S.act_nn[j] & ~nv;
-            }
-            if (nx) P.nxt[idx] = 0;
-            anyf |= fnew;
+        for (int k = 0; k < TG; k++) {
+          if (t0 + k >= P.tiles) break;
+          const int j = (t0 + k) * T + gl;
+          const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
+          const uint64_t nx = nxv[k];
+          const int nl = S.newlvl[j];
+          const uint64_t old = nl ? oldv[k] : 0ull;
+          const uint64_t fnew = nx & ~old & S.act_new[j];
+          const uint64_t nv = old | fnew;
+          if (nl == 0) {
+            P.vis[idx] = nv;
+            for (int b = 0; b < P.B; b++) P.planes[b * P.pstride + idx] = 0;
+          } else if (fnew) {
+            P.vis[idx] = nv;
+            for (int b = 0; b < P.B; b++)
+              if ((nl >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
           }
+          if (S.write_next) {
+            S.fr_next[idx] = fnew;
+            if (t0 + k < TG) live_acc[k] |= fnew;
+            else if (fnew) atomicOr((unsigned long long *)&s_live[j], fnew);
+            anyneed |= S.act_nn[j] & ~nv;
+          }
+          if (nx) P.nxt[idx] = 0;
+          anyf |= fnew;
         }
       }
-      const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
-      const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
-      const bool take = valid && gl == 0 && fflag;
-      if (valid && gl == 0 && nflag) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
-      const int32_t indeg = take ? P.rev_ptr[v + 1] - P.rev_ptr[v] : 0;
-      const uint64_t bal = __ballot(take);
-      const int32_t wpre = __popcll(bal & ((1ull << lane) - 1ull));
-      const int32_t eincl = wave_incl_scan(indeg, lane);
-      if (lane == 63) { s_wcnt[wid] = __popcll(bal); s_wedge[wid] = eincl; }
-      __syncthreads();
-      if (take) {
-        int32_t cpre = s_cnt, epre = s_edges;
-        for (int w = 0; w < wid; w++) { cpre += s_wcnt[w]; epre += s_wedge[w]; }
-        s_lv[cpre + wpre] = (int32_t)v;
-        s_le[cpre + wpre] = epre + eincl - indeg;
-      }
-      __syncthreads();
-      if (tid == 0)
-        for (int w = 0; w < BLOCK / 64; w++) { s_cnt += s_wcnt[w]; s_edges += s_wedge[w]; }
-      __syncthreads();
     }
-    if (tid == 0)
-      s_base = s_cnt ? atomicAdd((unsigned long long *)&st[0],
-                                 (unsigned long long)(((uint64_t)s_cnt << 32) | (uint32_t)s_edges))
-                     : 0ull;
-    __syncthreads();
-    if (S.build_list) {
-      const int32_t bc = (int32_t)(s_base >> 32), be = (int32_t)(uint32_t)s_base;
-      for (int i = tid; i < s_cnt; i += BLOCK) {
-        P.flist[bc + i] = s_lv[i];
-        P.flist_eoff[bc + i] = be + s_le[i];
-      }
+    const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
+    const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
+    if (valid && gl == 0) {
+      if (S.build_list) S.flags_next[v] = fflag ? 1 : 0;
+      if (fflag) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
+      if (nflag) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
     }
-    __syncthreads();
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nf_acc += __shfl_xor(nf_acc, off);
+    mf_acc += __shfl_xor(mf_acc, off);
+    mu_acc += __shfl_xor(mu_acc, off);
+  }
+  if (lane == 0) {
+    uint64_t *st = stat_stripe(S.st_out, blockIdx.x);
+    if (nf_acc) atomicAdd((unsigned long long *)&st[0], (unsigned long long)((nf_acc << 32) | mf_acc));
+    if (mu_acc && S.write_next) atomicAdd((unsigned long long *)&st[1], (unsigned long long)mu_acc);
   }
   if (S.write_next) {
+#pragma unroll
+    for (int k = 0; k < TG; k++)   // OR over threads that own the same word, then one LDS atomic
+      if (k < P.tiles) {
+        uint64_t x = live_acc[k];
+        for (int off = G; off < 64; off <<= 1) x |= __shfl_xor(x, off);
+        if (lane < G && x) atomicOr((unsigned long long *)&s_live[k * T + gl], x);
+      }
     __syncthreads();
     for (int j = tid; j < P.Wp; j += BLOCK)
       if (s_live[j]) atomicOr((unsigned long long *)&S.live_out[j], s_live[j]);
-    for (int off = 32; off > 0; off >>= 1) mu_acc += __shfl_xor(mu_acc, off);
-    if (lane == 0 && mu_acc) atomicAdd((unsigned long long *)&st[1], (unsigned long long)mu_acc);
+  }
+}
+
+// ---- compact: the frontier list (vertex, offset of its in-edges) from the
+// frontier flags, for a level that expands by push. Wavefront ballot and
+// prefix sums into LDS per chunk of CMP_CHUNK vertices; one global
+// reservation per chunk.
+constexpr int CMP_CHUNK = 2048;
+
+__global__ __launch_bounds__(BLOCK) void k_compact(const Pass P, const Step S) {
+  if (pick_dir(S.st_in, P.alpha, P.force_dir) != 1) return;
+  __shared__ int32_t s_lv[CMP_CHUNK], s_le[CMP_CHUNK];
+  __shared__ unsigned long long s_acc, s_base;
+  const int tid = threadIdx.x, lane = tid & 63;
+  unsigned long long *cnt = (unsigned long long *)&S.st_in[2];   // list reservation counter (stripe 0)
+  const int64_t nchunks = ((int64_t)P.n + CMP_CHUNK - 1) / CMP_CHUNK;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    if (tid == 0) s_acc = 0;
+    __syncthreads();
+    const int64_t c0 = c * CMP_CHUNK, c1 = min((int64_t)P.n, c0 + CMP_CHUNK);
+    for (int64_t vb = c0; vb < c1; vb += BLOCK) {
+      const int64_t v = vb + tid;
+      const bool take = v < c1 && S.flags_cur[v];
+      const int32_t indeg = take ? P.rev_ptr[v + 1] - P.rev_ptr[v] : 0;
+      const uint64_t bal = __ballot(take);
+      const int32_t eincl = wave_incl_scan(indeg, lane);
+      const int32_t wcnt = __popcll(bal), wedge = __shfl(eincl, 63);
+      unsigned long long base = 0;
+      if (lane == 0 && wcnt) base = atomicAdd(&s_acc, ((unsigned long long)wcnt << 32) | (uint32_t)wedge);
+      base = __shfl(base, 0);
+      if (take) {
+        const int32_t pos = (int32_t)(base >> 32) + __popcll(bal & ((1ull << lane) - 1ull));
+        s_lv[pos] = (int32_t)v;
+        s_le[pos] = (int32_t)(uint32_t)base + eincl - indeg;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_base = s_acc ? atomicAdd(cnt, s_acc) : 0ull;
+    __syncthreads();
+    const int32_t n_in = (int32_t)(s_acc >> 32);
+    const int32_t bc = (int32_t)(s_base >> 32), be = (int32_t)(uint32_t)s_base;
+    for (int i = tid; i < n_in; i += BLOCK) {
+      P.flist[bc + i] = s_lv[i];
+      P.flist_eoff[bc + i] = be + s_le[i];
+    }
+    __syncthreads();
   }
 }
 
@@ -184,10 +240,10 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
 // Wq threads per edge cover the words (power of two, <= 64).
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_push(const Pass P, const Step S, int Wq) {
-  const uint64_t *st = S.st_in;
-  if (pick_dir(st, P.alpha, P.force_dir) != 1) return;
-  const int32_t nf = (int32_t)(st[0] >> 32);
-  const int64_t mf = (int64_t)(uint32_t)st[0];
+  uint32_t nf_u = 0, mf_u = 0;
+  if (pick_dir(S.st_in, P.alpha, P.force_dir, &nf_u, &mf_u) != 1) return;
+  const int32_t nf = (int32_t)nf_u;
+  const int64_t mf = (int64_t)mf_u;
   const int EPB = BLOCK / Wq;
   const int tid = threadIdx.x, wq = tid & (Wq - 1), es = tid / Wq;
   const uint64_t *fr = S.fr_cur;
@@ -255,9 +311,11 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
         const int32_t e = e0 + u * E + eo;
         x[u] = e < ee ? col[e] : -1;
       }
+      // a thread whose word has found every missing lane stops gathering
+      const bool want = (acc & need) != need;
 #pragma unroll
       for (int u = 0; u < U; u++)
-        if (x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
+        if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
       uint64_t r = acc;
 #pragma unroll
       for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
@@ -300,21 +358,20 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
   else pull_rows<T, 64, false>(P, S, items, n_items, tile, bb, bpt);
 }
 
-// ---- score: per vertex and query, root test, score histogram per chunk and
-// the scanned-edge count te (in-degree of every vertex each lane expanded).
-// Each thread holds SC_R vertices; a wavefront walks the words and their
-// queries in lockstep, so histogram updates are aggregated per distinct
-// score value and te is reduced across the wavefront once per query.
-constexpr int SC_R = 2;
-
+// ---- score: per vertex and query, root test and score histogram per chunk;
+// optionally the scanned-edge count te (in-degree of every vertex each lane
+// expanded). A thread owns one vertex and holds the T words of one tile
+// (vis and distance planes) in registers; a wavefront walks the words and
+// their queries in lockstep; histogram counts are LDS atomics (the LDS unit
+// serialises equal addresses, which costs less than aggregating in code).
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;
   int32_t *s_hist = (int32_t *)(s_dyn + (P.te_lds ? P.nq : 0));
   const int tid = threadIdx.x, lane = tid & 63;
-  const int split = (P.CH + BLOCK * SC_R - 1) / (BLOCK * SC_R);
-  if (P.te_lds)
+  const int split = (P.CH + BLOCK - 1) / BLOCK;
+  if (P.count_te && P.te_lds)
     for (int i = tid; i < P.nq; i += BLOCK) s_te[i] = 0;
   for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
     const int c = (int)(bid / split), part = (int)(bid % split);
@@ -323,58 +380,47 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
     __syncthreads();
     int32_t *hist = P.hist_lds ? s_hist : P.hist + (size_t)c * P.nhist;
     const int64_t cend = min((int64_t)P.n, (int64_t)(c + 1) * P.CH);
-    const int64_t v0 = (int64_t)c * P.CH + (int64_t)part * BLOCK * SC_R;
-    int64_t vv[SC_R];
-    uint64_t indeg[SC_R];
+    const int64_t v = (int64_t)c * P.CH + (int64_t)part * BLOCK + tid;
+    const bool valid = v < cend;
+    const uint64_t indeg = (valid && P.count_te) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
+    for (int tile = 0; tile < P.tiles; tile++) {
+      if (P.word_q_ptr[tile * T] == P.word_q_ptr[(tile + 1) * T]) continue;   // no query in this tile
+      const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T;
+      uint64_t vis[T], pl[4][T];
 #pragma unroll
-    for (int r = 0; r < SC_R; r++) {
-      vv[r] = v0 + r * BLOCK + tid;
-      indeg[r] = vv[r] < cend ? (uint64_t)(P.rev_ptr[vv[r] + 1] - P.rev_ptr[vv[r]]) : 0ull;
-    }
-    for (int j = 0; j < P.Wp; j++) {
-      const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
-      if (qb == qe) continue;
-      const size_t base = (size_t)(j / T) * P.n * T + (j % T);
-      uint64_t vis[SC_R], pl[SC_R][4];
-      bool any = false;
+      for (int w = 0; w < T; w++) vis[w] = valid ? P.vis[base + w] : 0ull;
 #pragma unroll
-      for (int r = 0; r < SC_R; r++) {
-        vis[r] = vv[r] < cend ? P.vis[base + (size_t)vv[r] * T] : 0ull;
-        for (int b = 0; b < 4; b++)
-          pl[r][b] = (b < P.B && vis[r]) ? P.planes[b * P.pstride + base + (size_t)vv[r] * T] : 0ull;
-        any |= vis[r] != 0;
-      }
-      if (__ballot(any) == 0) continue;
-      for (int qi = qb; qi < qe; qi++) {
-        const int q = P.word_q[qi];
-        const uint64_t m = P.q_mask[q];
-        const int dq = P.q_dmax[q], hq = P.q_hoff[q];
-        uint64_t t = 0;
+      for (int b = 0; b < 4; b++)
 #pragma unroll
-        for (int r = 0; r < SC_R; r++) {
-          const uint64_t x = vis[r] & m;
-          uint64_t eq = x;
-          for (int b = 0; b < P.B; b++) eq &= ((dq >> b) & 1) ? pl[r][b] : ~pl[r][b];
-          t += (uint64_t)(__popcll(x) - __popcll(eq)) * indeg[r];
-          const bool root = x == m;
+        for (int w = 0; w < T; w++) pl[b][w] = (valid && b < P.B) ? P.planes[b * P.pstride + base + w] : 0ull;
+#pragma unroll
+      for (int w = 0; w < T; w++) {
+        const int j = tile * T + w;
+        const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
+        if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
+        for (int qi = qb; qi < qe; qi++) {
+          const int q = P.word_q[qi];
+          const uint64_t m = P.q_mask[q], x = vis[w] & m;
+          if (P.count_te) {
+            const int dq = P.q_dmax[q];
+            uint64_t eq = x;
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+              if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
+            uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
+            if (__ballot(t != 0)) {
+              for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+              if (lane == 0) {
+                if (P.te_lds) atomicAdd((unsigned long long *)&s_te[q], (unsigned long long)t);
+                else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
+              }
+            }
+          }
+          const bool root = x == m && valid;
           int sc = 0;
-          if (root)
-            for (int b = 0; b < P.B; b++) sc += __popcll(pl[r][b] & m) << b;
-          uint64_t pend = __ballot(root);
-          while (pend) {
-            const int leader = __ffsll((long long)pend) - 1;
-            const int sv = __shfl(sc, leader);
-            const uint64_t same = __ballot(root && sc == sv);
-            if (lane == leader) atomicAdd(&hist[hq + sv], (int)__popcll(same));
-            pend &= ~same;
-          }
-        }
-        if (__ballot(t != 0)) {
-          for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-          if (lane == 0) {
-            if (P.te_lds) atomicAdd((unsigned long long *)&s_te[q], (unsigned long long)t);
-            else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
-          }
+#pragma unroll
+          for (int b = 0; b < 4; b++) sc += __popcll(pl[b][w] & m) << b;   // planes past B are zero
+          if (root) atomicAdd(&hist[P.q_hoff[q] + sc], 1);
         }
       }
     }
@@ -384,7 +430,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
         if (s_hist[i]) atomicAdd(&P.hist[(size_t)c * P.nhist + i], s_hist[i]);
     __syncthreads();
   }
-  if (P.te_lds) {
+  if (P.count_te && P.te_lds) {
     __syncthreads();
     for (int i = tid; i < P.nq; i += BLOCK)
       if (s_te[i]) atomicAdd((unsigned long long *)&P.te[i], (unsigned long long)s_te[i]);
@@ -538,16 +584,24 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const Pass P) {
   }
 }
 
-// ---- answer: one wave per (query, root, keyword) walks from the root to
+// ---- answer: one block per (query, root, keyword) walks from the root to
 // the smallest-id out-neighbour one hop closer, writing the path into the
 // keyword's segment of the root's edge slot; then one wave per (query, root)
 // merges the segments: sort, drop repeats.
+__device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) atomicMin(slot, v);
+  __syncthreads();
+  const int32_t r = *slot;
+  __syncthreads();
+  return r;
+}
+
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
-  constexpr int WAVES = BLOCK / 64;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t waves = (int64_t)gridDim.x * WAVES;
-  for (int64_t item = (int64_t)blockIdx.x * WAVES + wid; item < P.total_kd; item += waves) {
+  __shared__ int32_t s_best;
+  const int tid = threadIdx.x;
+  for (int64_t item = blockIdx.x; item < P.total_kd; item += gridDim.x) {
     int lo = 0, hi = P.nq;                      // query owning this (root, keyword) item
     while (hi - lo > 1) {
       int mid = (lo + hi) >> 1;
@@ -556,61 +610,55 @@ __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
     const int q = lo, nk = P.q_nk[q];
     const int rel = (int)(item - P.q_kdoff[q]), i = rel / nk, j = rel % nk;
     if (i >= P.qsel[q * 4 + 0]) continue;
-    const int32_t r = P.r_roots[P.q_roff[q] + i];
     int d = P.r_kwdist[item];
     const int word = P.q_word[q], w = word % T, bit = P.bits[P.q_boff[q] + j];
     const size_t tb = (size_t)(word / T) * P.n * T;
     int2 *out = P.r_edges + P.q_eoff[q] + (size_t)i * P.q_ecap[q] + (size_t)j * P.q_dmax[q];
-    int32_t x = r;
-    int h = 0;
     const int32_t sb = P.qk_seed_b[P.q_boff[q] + j];
     const int64_t ns = P.qk_seed_e[P.q_boff[q] + j] - sb;
+    int32_t x = P.r_roots[P.q_roff[q] + i];
+    int h = 0;
     while (d > 0) {
-      int32_t best = 0x7fffffff;
       const int32_t e0 = P.fwd_ptr[x], e1 = P.fwd_ptr[x + 1];
+      if (tid == 0) s_best = 0x7fffffff;
+      __syncthreads();
+      int32_t best = 0x7fffffff;
       if (d == 1 && ns * 4 < (int64_t)(e1 - e0)) {
         // last hop: the keyword's vertices are few compared with the row, so
         // look each of them up in the sorted row and keep the smallest hit
-        const int32_t *seeds = P.inv_vtx + sb;
         int32_t mine = 0x7fffffff;
-        for (int64_t k = lane; k < ns; k += 64) {
-          const int32_t v = seeds[k];
-          int32_t lo = e0, hi = e1;
-          while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (P.fwd_col[mid] < v) lo = mid + 1; else hi = mid;
+        for (int64_t k = tid; k < ns; k += BLOCK) {
+          const int32_t v = P.inv_vtx[sb + k];
+          int32_t a = e0, b = e1;
+          while (a < b) {
+            const int32_t mid = (a + b) >> 1;
+            if (P.fwd_col[mid] < v) a = mid + 1; else b = mid;
           }
-          if (lo < e1 && P.fwd_col[lo] == v) mine = min(mine, v);
+          if (a < e1 && P.fwd_col[a] == v) mine = min(mine, v);
         }
-        for (int off = 32; off > 0; off >>= 1) mine = min(mine, __shfl_xor(mine, off));
-        best = mine;
+        best = block_min(mine, &s_best);
       } else {
-        // rows are sorted by neighbour id, so the first qualifying neighbour
-        // in row order is the smallest-id one; four chunks of 64 per round
+        // rows are sorted by neighbour id, so the qualifying neighbours of
+        // the first round that has any include the smallest-id one
         constexpr int U = 4;
-        for (int32_t eb = e0; eb < e1 && best == 0x7fffffff; eb += 64 * U) {
-          int32_t y[U];
-          bool ok[U];
+        for (int32_t eb = e0; eb < e1; eb += BLOCK * U) {
+          int32_t y[U], mine = 0x7fffffff;
 #pragma unroll
           for (int u = 0; u < U; u++) {
-            const int32_t e = eb + u * 64 + lane;
+            const int32_t e = eb + u * BLOCK + tid;
             y[u] = e < e1 ? P.fwd_col[e] : -1;
           }
 #pragma unroll
           for (int u = 0; u < U; u++)
-            ok[u] = y[u] >= 0 && ((P.vis[tb + (size_t)y[u] * T + w] >> bit) & 1ull);
-#pragma unroll
-          for (int u = 0; u < U; u++)
-            if (ok[u]) ok[u] = lane_dist(P, tb + (size_t)y[u] * T + w, bit) == d - 1;
-#pragma unroll
-          for (int u = 0; u < U; u++) {
-            const uint64_t bal = __ballot(ok[u]);
-            if (bal && best == 0x7fffffff) best = __shfl(y[u], __ffsll((long long)bal) - 1);
-          }
+            if (y[u] >= 0 && ((P.vis[tb + (size_t)y[u] * T + w] >> bit) & 1ull) &&
+                lane_dist(P, tb + (size_t)y[u] * T + w, bit) == d - 1)
+              mine = min(mine, y[u]);
+          best = block_min(mine, &s_best);
+          if (best != 0x7fffffff) break;
         }
       }
       if (best == 0x7fffffff || h >= P.q_dmax[q]) break;   // cannot happen for a BFS-consistent state
-      if (lane == 0) out[h] = make_int2(x, best);
+      if (tid == 0) out[h] = make_int2(x, best);
       h++;
       x = best;
       d--;
@@ -700,6 +748,7 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
   const int Wq = std::min(64, P.Wp < 2 ? 1 : 1 << (32 - __builtin_clz((unsigned)P.Wp - 1)));
   {
     Timer t(prof, s, KC_PUSH);
+    k_compact<<<clamp_grid(std::min<int64_t>(((int64_t)P.n + CMP_CHUNK - 1) / CMP_CHUNK, 4096)), BLOCK, 0, s>>>(P, S);
     k_push<T><<<2048, BLOCK, 0, s>>>(P, S, Wq);
   }
   KWS_TRY(launch_check("push"));
@@ -722,7 +771,7 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
 
 template <int T>
 kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
-  const unsigned grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + FIN_CHUNK - 1) / FIN_CHUNK, 8192));
+  const unsigned grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + BLOCK / T - 1) / (BLOCK / T), 1024));
   {
     Timer t(prof, s, KC_FINALIZE);
     k_finalize<T><<<grid, BLOCK, sizeof(uint64_t) * (size_t)P.Wp, s>>>(P, S);
@@ -736,7 +785,7 @@ kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
   {
     Timer t(prof, s, KC_SCORE);
     const size_t lds = (P.te_lds ? sizeof(uint64_t) * P.nq : 0) + (P.hist_lds ? sizeof(int32_t) * P.nhist : 0);
-    const int64_t split = (P.CH + BLOCK * SC_R - 1) / (BLOCK * SC_R);
+    const int64_t split = (P.CH + BLOCK - 1) / BLOCK;
     k_score<T><<<clamp_grid(P.chunks * split), BLOCK, lds, s>>>(P);
   }
   KWS_TRY(launch_check("score"));
@@ -758,7 +807,7 @@ kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
   {
     Timer t(prof, s, KC_ANSWER);
     const int64_t waves = BLOCK / 64;
-    k_answer<T><<<clamp_grid((P.total_kd + waves - 1) / waves), BLOCK, 0, s>>>(P);
+    k_answer<T><<<clamp_grid(P.total_kd), BLOCK, 0, s>>>(P);
     k_answer_merge<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
   }
   return launch_check("answer");

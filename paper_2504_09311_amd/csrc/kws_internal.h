@@ -85,6 +85,9 @@ constexpr int32_t BIN_LARGE_MAX = 4096;
 constexpr int32_t HUB_CHUNK = 4096;
 
 constexpr int MAX_WORDS = 1024;      // words per device pass (65536 lanes)
+constexpr int STAT_STRIPES = 32;     // frontier statistics: stripes of STAT_STRIDE words
+constexpr int STAT_STRIDE = 16;      // one 128-byte line per stripe
+constexpr int STAT_WORDS = STAT_STRIPES * STAT_STRIDE;
 constexpr int BLOCK = 256;
 
 // ---------------------------------------------------------------- engine state
@@ -93,6 +96,7 @@ struct Engine {
   DevBuf vis, fr0, fr1, nxt, planes;   // planes: [4][tiles][n][T]
   size_t state_words = 0;              // words per array currently allocated (n * Wp)
   DevBuf flist, flist_eoff;            // frontier list and in-edge offsets
+  DevBuf flags;                        // [2][n] frontier flags (current, next)
   DevBuf plan;                         // per-pass plan (device copy)
   DevBuf zero_region;                  // per-pass counters zeroed by the seed kernel
   DevBuf qsel;                         // per-query top-k threshold

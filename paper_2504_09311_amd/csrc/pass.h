@@ -21,7 +21,7 @@ struct Pass {
   // sizes
   int32_t n, T, tiles, Wp, B, nq, n_lanes;
   int32_t chunks, CH, nhist, hist_lds, te_lds;
-  int32_t force_dir;
+  int32_t force_dir, count_te;
   float alpha;
   int64_t total_seeds, n_hub, total_slots, total_kd;
   int64_t bin_begin[BIN_COUNT + 1];
@@ -66,9 +66,11 @@ struct Pass {
 struct Step {
   const uint64_t *act_exp;   // [Wp] lanes that expand in this step
   const uint64_t *live_in;   // [Wp] lanes whose current frontier is non-empty
-  const uint64_t *st_in;     // statistics of the current frontier (direction choice)
+  const uint64_t *st_in;     // statistics of the current frontier: (n_f << 32 | m_f), m_u, list counter
   const uint64_t *fr_cur;
   uint64_t *fr_next;
+  const uint8_t *flags_cur;  // [n] 1 if the vertex is in the frontier being expanded
+  uint8_t *flags_next;
   const uint64_t *act_new;   // [Wp] lanes allowed to gain a distance in this step
   const uint64_t *act_nn;    // [Wp] lanes that would expand in the following step
   const int8_t *newlvl;      // [Wp]

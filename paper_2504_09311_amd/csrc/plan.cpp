@@ -147,10 +147,13 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
   for (int j = 0; j < Wp; j++) wq_ptr[j + 1] += wq_ptr[j];
   std::vector<int32_t> fill(wq_ptr.begin(), wq_ptr.end() - 1);
   for (int i = 0; i < nq; i++) wq[fill[word[i]]++] = i;
-  chunks = (int)std::min<int64_t>(512, std::max<int64_t>(1, ((int64_t)n + 2047) / 2048));
+  // chunks of at most 8192 vertices (the select step scans whole chunks),
+  // at least 2048, and no more than 4096 of them (histograms per chunk)
+  chunks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, std::max<int64_t>(((int64_t)n + 8191) / 8192,
+                                                                              std::min<int64_t>(512, ((int64_t)n + 2047) / 2048))));
   CH = (int)align_up((size_t)((n + chunks - 1) / chunks), 64);
   chunks = (n + CH - 1) / CH;
-  hist_lds = nhist <= 8192;
+  hist_lds = nhist <= 16384;
   te_lds = nq <= 2048;
   if ((size_t)chunks * (size_t)nhist > (size_t)INT32_MAX) return fail(KWS_EOVERFLOW, "histogram too large");
   return KWS_OK;
@@ -246,6 +249,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.hist_lds = Q.hist_lds;
   P.te_lds = Q.te_lds;
   P.force_dir = g->opt.direction;
+  P.count_te = g->opt.count_te > 0;
   P.alpha = g->opt.alpha;
   P.total_seeds = L.seed_off.back();
   P.n_hub = g->n_hub;
@@ -303,7 +307,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
 }
 
 kws_status collect_results(const QueryTables &Q, const std::vector<const QIn *> &qs, const uint8_t *ha,
-                           const ArenaLayout &al, kws_result *const *out, FlatOut *flat) {
+                           const ArenaLayout &al, bool te_counted, kws_result *const *out, FlatOut *flat) {
   const uint64_t *h_te = (const uint64_t *)(ha + al.te);
   const int32_t *h_nroots = (const int32_t *)(ha + al.nroots);
   const int32_t *h_roots = (const int32_t *)(ha + al.roots);
@@ -329,14 +333,14 @@ kws_status collect_results(const QueryTables &Q, const std::vector<const QIn *> 
         for (int t = 0; t < c; t++) { F.edge_src.push_back(src[t].x); F.edge_dst.push_back(src[t].y); }
         F.edge_ptr.push_back((int64_t)F.edge_src.size());
       }
-      F.te.push_back((int64_t)h_te[i]);
+      F.te.push_back(te_counted ? (int64_t)h_te[i] : -1);
       continue;
     }
     kws_result &r = *out[i];
     std::memset(&r, 0, sizeof(r));
     r.n_roots = nr;
     r.n_kw = qi.nk;
-    r.te = (int64_t)h_te[i];
+    r.te = te_counted ? (int64_t)h_te[i] : -1;
     int64_t ne = 0;
     for (int j = 0; j < nr; j++) ne += h_ecount[Q.roff[i] + j];
     r.kw = (int32_t *)malloc(sizeof(int32_t) * (size_t)std::max(1, qi.nk));

@@ -81,6 +81,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   KWS_TRY(ensure_state(E, (size_t)n * Wp, g->stream));
   KWS_TRY(E.flist.ensure(sizeof(int32_t) * (size_t)n, "frontier list"));
   KWS_TRY(E.flist_eoff.ensure(sizeof(int32_t) * (size_t)n, "frontier offsets"));
+  KWS_TRY(E.flags.ensure(2 * (size_t)n, "frontier flags"));
 
   LaneTables L;
   for (const LaneInfo &li : pk.lanes) L.add(g, li);
@@ -95,7 +96,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   QueryTables Q;
   KWS_TRY(Q.build(g, qp, pk.placed, Wp));
 
-  const ArenaLayout al = arena_layout(Q, 0, (size_t)(D + 1) * Wp, (size_t)(D + 1) * 4);
+  const ArenaLayout al = arena_layout(Q, 0, (size_t)(D + 1) * Wp, (size_t)(D + 1) * STAT_WORDS);
   KWS_TRY(E.arena.ensure(al.size, "result arena"));
   KWS_TRY(E.h_arena.ensure(al.size, "result arena (host)"));
   KWS_TRY(E.zero_region.ensure(al.z_size, "counters"));
@@ -123,14 +124,16 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
     if (lv >= 0) {
       S.act_exp = act_d + (size_t)(lv + 1) * Wp;
       S.live_in = live + (size_t)lv * Wp;
-      S.st_in = stats + (size_t)lv * 4;
+      S.st_in = stats + (size_t)lv * STAT_WORDS;
       S.fr_cur = (lv & 1) ? P.fr1 : P.fr0;
+      S.flags_cur = E.flags.as<uint8_t>() + (size_t)(lv & 1) * n;
     }
     S.fr_next = ((lv + 1) & 1) ? P.fr1 : P.fr0;
+    S.flags_next = E.flags.as<uint8_t>() + (size_t)((lv + 1) & 1) * n;
     S.act_new = act_d + (size_t)(lv + 1) * Wp;
     S.act_nn = act_d + (size_t)(lv + 2) * Wp;
     S.newlvl = lvl_d + (size_t)(lv + 1) * Wp;
-    S.st_out = stats + (size_t)(lv + 1) * 4;
+    S.st_out = stats + (size_t)(lv + 1) * STAT_WORDS;
     S.live_out = live + (size_t)(lv + 1) * Wp;
     S.build_list = S.write_next = lv + 1 < D;
     steps.push_back(S);
@@ -156,7 +159,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
 
   std::vector<kws_result *> outs(nq);
   for (int i = 0; i < nq; i++) outs[i] = out ? &out[qa + i] : nullptr;
-  KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, outs.data(), flat));
+  KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, P.count_te != 0, outs.data(), flat));
 
   const uint64_t *h_stats = (const uint64_t *)(E.h_arena.as<uint8_t>() + al.extra);
   kws_batch_stats &bs = g->last;
@@ -170,15 +173,19 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   bs.levels = std::max(bs.levels, D);
   bs.passes += 1;
   for (int lv = 0; lv <= D && lv <= KWS_MAX_DMAX; lv++) {
-    const uint64_t packed = h_stats[lv * 4];
+    uint64_t packed = 0, mu = 0;
+    for (int k = 0; k < STAT_STRIPES; k++) {
+      packed += h_stats[(size_t)lv * STAT_WORDS + (size_t)k * STAT_STRIDE];
+      mu += h_stats[(size_t)lv * STAT_WORDS + (size_t)k * STAT_STRIDE + 1];
+    }
     const uint32_t nf = (uint32_t)(packed >> 32), mf = (uint32_t)packed;
     bs.frontier[lv] += nf;
     bs.frontier_edges[lv] += mf;
-    bs.unfinished_edges[lv] += (int64_t)h_stats[lv * 4 + 1];
+    bs.unfinished_edges[lv] += (int64_t)mu;
     if (lv == D) break;
     int dir = 0;
     if (nf) dir = (o.direction == 1 || o.direction == 2) ? o.direction
-                  : ((double)o.alpha * mf > (double)h_stats[lv * 4 + 1] ? 2 : 1);
+                  : ((double)o.alpha * mf > (double)mu ? 2 : 1);
     bs.pulled[lv] |= dir == 2;
   }
   return KWS_OK;
@@ -194,6 +201,7 @@ void default_options(kws_options *o) {
   o->block = BLOCK;
   o->use_graph = 0;
   o->share_lanes = 1;
+  o->count_te = 0;
 }
 
 kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out, FlatOut *flat) {

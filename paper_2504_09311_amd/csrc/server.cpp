@@ -63,7 +63,7 @@ struct kws_server {
   hipStream_t stream = nullptr;
   int T = 8, tiles_alloc = 1, words = 1, B = 4;
   std::vector<kws::Slot> slots;
-  kws::DevBuf live, stats;        // [2][Wp] and [2][4], ping-pong across steps
+  kws::DevBuf live, stats;        // [2][Wp] and [2][STAT_WORDS], ping-pong across steps
   int64_t step_no = 0;
 
   std::thread worker;
@@ -203,18 +203,20 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
   std::memset(&S, 0, sizeof(S));
   S.act_exp = pw.dev<uint64_t>(E, o_exp);
   S.live_in = live + (size_t)par * wstride;
-  S.st_in = stats + (size_t)par * 4;
+  S.st_in = stats + (size_t)par * STAT_WORDS;
   S.fr_cur = par ? P.fr1 : P.fr0;
   S.fr_next = par ? P.fr0 : P.fr1;
+  S.flags_cur = E.flags.as<uint8_t>() + (size_t)par * n;
+  S.flags_next = E.flags.as<uint8_t>() + (size_t)(1 - par) * n;
   S.act_new = pw.dev<uint64_t>(E, o_new);
   S.act_nn = pw.dev<uint64_t>(E, o_nn);
   S.newlvl = pw.dev<int8_t>(E, o_lvl);
-  S.st_out = stats + (size_t)(1 - par) * 4;
+  S.st_out = stats + (size_t)(1 - par) * STAT_WORDS;
   S.live_out = live + (size_t)(1 - par) * wstride;
   S.build_list = 1;
   S.write_next = 1;
   // the step's output statistics are cleared with the counters
-  KWS_HIP(hipMemsetAsync(S.st_out, 0, 4 * sizeof(uint64_t), s->stream));
+  KWS_HIP(hipMemsetAsync(S.st_out, 0, STAT_WORDS * sizeof(uint64_t), s->stream));
   KWS_TRY(launch_seed(P, s->stream, s->prof));
   if (any_expand) KWS_TRY(launch_expand(P, S, s->stream, s->prof));
   KWS_TRY(launch_finalize(P, S, s->stream, s->prof));
@@ -228,7 +230,7 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
     std::vector<kws_result> res(Q.nq);
     std::vector<kws_result *> outs(Q.nq);
     for (int i = 0; i < Q.nq; i++) outs[i] = &res[i];
-    KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, outs.data(), nullptr));
+    KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, P.count_te != 0, outs.data(), nullptr));
     for (int i = 0; i < Q.nq; i++) done_out.push_back({qtickets[i], res[i]});
   }
   // advance the slots
@@ -356,11 +358,12 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   kws_status st = kws::ensure_state(s->eng, (size_t)g->n * wp_alloc, s->stream);
   if (st == KWS_OK) st = s->eng.flist.ensure(sizeof(int32_t) * (size_t)g->n, "frontier list");
   if (st == KWS_OK) st = s->eng.flist_eoff.ensure(sizeof(int32_t) * (size_t)g->n, "frontier offsets");
+  if (st == KWS_OK) st = s->eng.flags.ensure(2 * (size_t)g->n, "frontier flags");
   if (st == KWS_OK) st = s->live.ensure(2 * wp_alloc * 8, "live lanes");
-  if (st == KWS_OK) st = s->stats.ensure(8 * 8, "step statistics");
+  if (st == KWS_OK) st = s->stats.ensure(2 * kws::STAT_WORDS * 8, "step statistics");
   if (st == KWS_OK && hipMemsetAsync(s->live.p, 0, 2 * wp_alloc * 8, s->stream) != hipSuccess)
     st = kws::fail(KWS_EDEVICE, "clearing server state failed");
-  if (st == KWS_OK && hipMemsetAsync(s->stats.p, 0, 64, s->stream) != hipSuccess)
+  if (st == KWS_OK && hipMemsetAsync(s->stats.p, 0, 2 * kws::STAT_WORDS * 8, s->stream) != hipSuccess)
     st = kws::fail(KWS_EDEVICE, "clearing server state failed");
   if (st == KWS_OK && hipStreamSynchronize(s->stream) != hipSuccess)
     st = kws::fail(KWS_EDEVICE, "server set-up failed");

@@ -18,6 +18,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <omp.h>
 
 #define GOLDEN 0x9E3779B97F4A7C15ULL
 
@@ -131,6 +132,47 @@ static inline void rmat_sample(uint64_t key, uint64_t i, int scale, double a, do
   *u_out = (int32_t)u; *v_out = (int32_t)v;
 }
 
+/* Parallel LSD radix sort of 64-bit keys on their low `bits` bits, 11 bits
+ * per pass; the result ends up in keys[]. */
+static void radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t len, int bits) {
+  enum { RB = 11, NB = 1 << RB };
+  int nth = 1;
+  #pragma omp parallel
+  {
+    #pragma omp single
+    nth = omp_get_num_threads();
+  }
+  int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)nth * NB);
+  uint64_t *src = keys, *dst = tmp;
+  int passes = (bits + RB - 1) / RB;
+  for (int p = 0; p < passes; p++) {
+    const int shift = p * RB;
+    memset(cnt, 0, sizeof(int64_t) * (size_t)nth * NB);
+    #pragma omp parallel num_threads(nth)
+    {
+      const int t = omp_get_thread_num();
+      const int64_t lo = len * t / nth, hi = len * (t + 1) / nth;
+      int64_t *c = cnt + (size_t)t * NB;
+      for (int64_t i = lo; i < hi; i++) c[(src[i] >> shift) & (NB - 1)]++;
+      #pragma omp barrier
+      #pragma omp single
+      {
+        int64_t acc = 0;
+        for (int d = 0; d < NB; d++)
+          for (int u = 0; u < nth; u++) {
+            int64_t x = cnt[(size_t)u * NB + d];
+            cnt[(size_t)u * NB + d] = acc;
+            acc += x;
+          }
+      }
+      for (int64_t i = lo; i < hi; i++) dst[c[(src[i] >> shift) & (NB - 1)]++] = src[i];
+    }
+    uint64_t *x = src; src = dst; dst = x;
+  }
+  if (src != keys) memcpy(keys, src, sizeof(uint64_t) * (size_t)len);
+  free(cnt);
+}
+
 /*
  * R-MAT(a,b,c,d=1-a-b-c) with 2^scale vertices and n_samples sampled edges
  * (Chakrabarti, Zhan and Faloutsos, SDM 2004), no noise. Vertex ids are
@@ -144,32 +186,33 @@ int64_t syn_rmat_csr(int32_t scale, int64_t n_samples, double a, double b, doubl
   int32_t n = (int32_t)1 << scale;
   uint64_t key = sm_key(seed, ST_RMAT);
   int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-  int64_t *ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_samples > 0 ? n_samples : 1));
-  if (!perm || !ptr || !tmp) { free(perm); free(ptr); free(tmp); return -1; }
+  uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n_samples > 0 ? n_samples : 1));
+  uint64_t *tmp = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n_samples > 0 ? n_samples : 1));
+  if (!perm || !keys || !tmp) { free(perm); free(keys); free(tmp); return -1; }
   make_perm(n, seed, ST_VPERM, perm);
   double ab = a + b, abc = a + b + c;
-  /* pass 1: out-degree counts */
   #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n_samples; i++) {
     int32_t u, v;
     rmat_sample(key, (uint64_t)i, scale, a, ab, abc, &u, &v);
-    __atomic_fetch_add(&ptr[perm[u] + 1], 1, __ATOMIC_RELAXED);
+    keys[i] = ((uint64_t)(uint32_t)perm[u] << scale) | (uint64_t)(uint32_t)perm[v];
   }
-  for (int32_t u = 0; u < n; u++) ptr[u + 1] += ptr[u];
-  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-  memcpy(cur, ptr, sizeof(int64_t) * (size_t)n);
-  /* pass 2: scatter (row order is fixed later by the per-row sort) */
-  #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n_samples; i++) {
-    int32_t u, v;
-    rmat_sample(key, (uint64_t)i, scale, a, ab, abc, &u, &v);
-    int64_t pos = __atomic_fetch_add(&cur[perm[u]], 1, __ATOMIC_RELAXED);
-    tmp[pos] = perm[v];
+  radix_sort_u64(keys, tmp, n_samples, 2 * scale);
+  free(tmp);
+  /* sorted by (u, v): drop self-loops and repeats while filling the CSR */
+  const uint64_t vmask = ((uint64_t)1 << scale) - 1;
+  int64_t m = 0, e = 0;
+  row_ptr[0] = 0;
+  for (int32_t u = 0; u < n; u++) {
+    while (e < n_samples && (int32_t)(keys[e] >> scale) == u) {
+      const uint64_t k = keys[e];
+      const int32_t v = (int32_t)(k & vmask);
+      if (v != u && (e == 0 || keys[e - 1] != k)) col[m++] = v;
+      e++;
+    }
+    row_ptr[u + 1] = (int32_t)m;
   }
-  free(cur);
-  int64_t m = clean_rows(n, ptr, tmp, row_ptr, col);
-  free(perm); free(ptr); free(tmp);
+  free(perm); free(keys);
   return m;
 }
 

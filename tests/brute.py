@@ -106,7 +106,7 @@ def certificate(row_ptr, col, in_set, dist, d_max):
          dist[w] == dist[u] - 1.
     Returns a list of violated condition numbers (empty = certified).
     """
-    dist = np.asarray(dist).astype(np.int64)
+    dist = np.asarray(dist).astype(np.int16)
     in_set = np.asarray(in_set, bool)
     n = dist.shape[0]
     bad = []
@@ -114,16 +114,21 @@ def certificate(row_ptr, col, in_set, dist, d_max):
         bad.append(1)
     if not np.all((dist <= d_max) | (dist == INF)):
         bad.append(2)
-    src = np.repeat(np.arange(n), np.diff(np.asarray(row_ptr, np.int64)))
-    dst = np.asarray(col, np.int64)
-    dw, du = dist[dst], dist[src]
-    sel = dw < d_max
-    if np.any(du[sel] > dw[sel] + 1):
-        bad.append(3)
-    good_edge = (du >= 1) & (du <= d_max) & (dw == du - 1)
+    row_ptr = np.asarray(row_ptr, np.int64)
     has = np.zeros(n, bool)
-    has[src[good_edge]] = True
+    chunk = 1 << 24                     # vertices per slice, keeps memory bounded at 1B edges
+    for v0 in range(0, n, chunk):
+        v1 = min(n, v0 + chunk)
+        a, b = int(row_ptr[v0]), int(row_ptr[v1])
+        src = np.repeat(np.arange(v0, v1, dtype=np.int64), np.diff(row_ptr[v0:v1 + 1]))
+        dst = np.asarray(col[a:b], np.int64)
+        dw, du = dist[dst], dist[src]
+        sel = dw < d_max
+        if 3 not in bad and np.any(du[sel] > dw[sel] + 1):
+            bad.append(3)
+        good_edge = (du >= 1) & (du <= d_max) & (dw == du - 1)
+        has[src[good_edge]] = True
     need = (dist >= 1) & (dist <= d_max)
     if np.any(need & ~has):
         bad.append(4)
-    return bad
+    return sorted(bad)
