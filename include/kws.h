@@ -169,6 +169,10 @@ typedef struct {
   int32_t share_lanes;   /* 1 (default): queries in one word share equal (keyword, d_max) lanes; -1: off */
   int32_t count_te;      /* 1: fill kws_result.te (costs a reduction per query in the score step);
                             0 (default): te = -1 */
+  int32_t seed_mode;     /* 0 auto; 1 scatter each lane's inverted-index slice (one atomic per
+                            (lane, vertex)); 2 every vertex looks its labels and their type
+                            ancestors up in a per-batch keyword hash. Auto takes 2 when the
+                            batch's seeds outnumber the vertices plus label-ancestor lookups */
 } kws_options;
 kws_status kws_set_options(kws_graph *g, const kws_options *opt);
 kws_status kws_get_options(kws_graph *g, kws_options *opt);

@@ -316,6 +316,8 @@ kws_status kws_set_options(kws_graph *g, const kws_options *opt) {
   o.use_graph = opt->use_graph > 0 ? 1 : 0;
   o.share_lanes = opt->share_lanes < 0 ? -1 : 1;
   o.count_te = opt->count_te > 0 ? 1 : 0;
+  if (opt->seed_mode < 0 || opt->seed_mode > 2) return kws::fail(KWS_EINVAL, "seed_mode must be 0, 1 or 2");
+  o.seed_mode = opt->seed_mode;
   std::lock_guard<std::mutex> lk(g->mu);
   g->opt = o;
   return KWS_OK;

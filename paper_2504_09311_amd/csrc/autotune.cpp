@@ -1,5 +1,5 @@
-// Autotuner: picks tile width and push/pull policy for a graph and batch
-// shape by timing a sample batch, and remembers the choice on disk.
+// Autotuner: picks tile width, push/pull policy and seeding mode for a graph
+// and batch shape by timing a sample batch, and remembers the choice on disk.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -41,7 +41,8 @@ bool cache_lookup(const char *path, const std::string &key, kws_options *o) {
     if (key != line) continue;
     kws_options t;
     default_options(&t);
-    if (sscanf(bar + 1, "direction=%d alpha=%f tile_words=%d", &t.direction, &t.alpha, &t.tile_words) == 3) {
+    if (sscanf(bar + 1, "direction=%d alpha=%f tile_words=%d seed_mode=%d", &t.direction, &t.alpha, &t.tile_words,
+               &t.seed_mode) >= 3) {
       *o = t;   // the last matching line wins
       found = true;
     }
@@ -53,7 +54,8 @@ bool cache_lookup(const char *path, const std::string &key, kws_options *o) {
 void cache_store(const char *path, const std::string &key, const kws_options &o, double ms) {
   FILE *f = path ? fopen(path, "a") : nullptr;
   if (!f) return;
-  fprintf(f, "%s|direction=%d alpha=%g tile_words=%d ms=%.4f\n", key.c_str(), o.direction, o.alpha, o.tile_words, ms);
+  fprintf(f, "%s|direction=%d alpha=%g tile_words=%d seed_mode=%d ms=%.4f\n", key.c_str(), o.direction, o.alpha,
+          o.tile_words, o.seed_mode, ms);
   fclose(f);
 }
 
@@ -119,6 +121,7 @@ extern "C" kws_status kws_autotune(kws_graph *g, const kws_query *qs, int32_t nq
   double best_ms = 0;
   kws_options best_o = d;
   kws_status st = KWS_OK;
+  const size_t n_main = grid.size();
   for (size_t i = 0; i < grid.size(); i++) {
     double ms = 0;
     kws::FlatOut ans;
@@ -132,14 +135,20 @@ extern "C" kws_status kws_autotune(kws_graph *g, const kws_query *qs, int32_t nq
       best_o = grid[0];
     } else {
       if (!kws::same_answers(ref, ans)) {
-        st = kws::fail(KWS_EDEVICE, "autotune: configuration %zu (tile %d, direction %d, alpha %g) changed the answers",
-                       i, grid[i].tile_words, grid[i].direction, grid[i].alpha);
+        st = kws::fail(KWS_EDEVICE, "autotune: configuration %zu (tile %d, direction %d, alpha %g, seed mode %d) "
+                       "changed the answers", i, grid[i].tile_words, grid[i].direction, grid[i].alpha, grid[i].seed_mode);
         break;
       }
       if (ms < best_ms) { best_ms = ms; best_o = grid[i]; }
     }
     const double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (budget_ms > 0 && spent > budget_ms) break;
+    if (i + 1 == n_main)
+      for (int sm : {1, 2}) {   // second phase: the best so far under each explicit seeding mode
+        kws_options o = best_o;
+        o.seed_mode = sm;
+        grid.push_back(o);
+      }
   }
   if (st != KWS_OK) {
     g->opt = saved;

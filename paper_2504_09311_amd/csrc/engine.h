@@ -39,8 +39,12 @@ void pack_queries(const std::vector<QIn> &qs, int qa, int qb, bool share, Packin
 // Seed tables of the lanes a pass starts: slice of the inverted index per lane.
 struct LaneTables {
   std::vector<int64_t> seed_off{0};
-  std::vector<int32_t> seed_begin, word, bit;
+  std::vector<int32_t> seed_begin, word, bit, kw;
+  // keyword hash for seeding by vertex (built by build_hash)
+  std::vector<int32_t> h_key, h_beg, h_cnt, e_word;
+  std::vector<uint64_t> e_mask;
   void add(const kws_graph *g, const LaneInfo &li);
+  void build_hash();
   int n() const { return (int)word.size(); }
 };
 
@@ -85,8 +89,8 @@ struct QueryOffsets {
 QueryOffsets add_query_tables(PlanWriter &pw, const QueryTables &Q);
 
 // Offsets of the lane seed tables inside the plan buffer.
-struct LaneOffsets { size_t seed_off, seed_begin, word, bit; };
-LaneOffsets add_lane_tables(PlanWriter &pw, const LaneTables &L);
+struct LaneOffsets { size_t seed_off, seed_begin, word, bit, h_key, h_beg, h_cnt, e_word, e_mask; };
+LaneOffsets add_lane_tables(PlanWriter &pw, LaneTables &L);
 
 // Fills the parts of a Pass common to batch and serving (graph, state,
 // lane and query tables, arena, counters); the caller sets the options.

@@ -191,7 +191,8 @@ kws_status validate(const kws_graph_desc *d) {
 // order. pre[t] is t's position; t and its descendants occupy
 // [pre[t], pre[t] + span[t]). Fails if the parents contain a cycle.
 kws_status type_preorder(const int32_t *parent, int32_t nt, std::vector<int32_t> &pre,
-                         std::vector<int32_t> &span) {
+                         std::vector<int32_t> &span, int32_t *depth) {
+  *depth = 0;
   pre.assign(nt, -1);
   span.assign(nt, 1);
   if (!parent) {
@@ -217,6 +218,7 @@ kws_status type_preorder(const int32_t *parent, int32_t nt, std::vector<int32_t>
         int32_t c = kids[top.second++];
         pre[c] = next++;
         stack.push_back({c, cptr[c]});
+        *depth = std::max(*depth, (int32_t)stack.size() - 1);
       } else {
         span[top.first] = next - pre[top.first];
         stack.pop_back();
@@ -255,7 +257,8 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   *out = nullptr;
   KWS_TRY(validate(d));
   std::vector<int32_t> pre, span;
-  KWS_TRY(type_preorder(d->type_parent, d->n_labels, pre, span));
+  int32_t depth = 0;
+  KWS_TRY(type_preorder(d->type_parent, d->n_labels, pre, span, &depth));
 
   kws_graph *g = new kws_graph();
   auto bail = [&](kws_status st) { free_graph(g); return st; };
@@ -263,6 +266,8 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   g->n = d->n;
   g->m = d->m;
   g->n_labels = d->n_labels;
+  g->h_lab_total = d->lab_ptr[d->n];
+  g->type_depth = depth;
   g->hier = d->type_parent != nullptr;
   g->pre = pre;
   g->span = span;
@@ -303,8 +308,11 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
 
   // inverted index over preorder keys
   int32_t *d_lab_ptr = nullptr, *d_lab = nullptr, *d_pre = nullptr, *keys = nullptr, *icnt = nullptr;
-  STEP(upload(&d_lab_ptr, d->lab_ptr, (size_t)n + 1, &scratch, "lab_ptr"));
-  STEP(upload(&d_lab, d->lab, (size_t)nl, &scratch, "lab"));
+  STEP(upload(&d_lab_ptr, d->lab_ptr, (size_t)n + 1, &bytes, "lab_ptr"));
+  STEP(upload(&d_lab, d->lab, (size_t)nl, &bytes, "lab"));
+  g->lab_ptr = d_lab_ptr;
+  g->lab = d_lab;
+  if (d->type_parent) STEP(upload(&g->tparent, d->type_parent, (size_t)g->n_labels, &bytes, "type parents"));
   STEP(upload(&d_pre, pre.data(), pre.size(), &scratch, "type preorder"));
   STEP(alloc_dev(&keys, (size_t)nl, &scratch, "label keys"));
   STEP(alloc_dev(&icnt, (size_t)g->n_labels + 1, &scratch, "label counts"));
@@ -324,7 +332,7 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   HSTEP(hipMemcpyAsync(g->h_inv_ptr.data(), g->inv_ptr, sizeof(int32_t) * ((size_t)g->n_labels + 1),
                        hipMemcpyDeviceToHost, s));
   HSTEP(hipStreamSynchronize(s));
-  dev_free(d_lab_ptr); dev_free(d_lab); dev_free(d_pre); dev_free(keys); dev_free(icnt);
+  dev_free(d_pre); dev_free(keys); dev_free(icnt);
 
   // degree facts and pull bins (host side: the CSR is already here)
   std::vector<int32_t> indeg(n, 0);
@@ -346,6 +354,10 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   }
   std::vector<int32_t> all;
   for (int b = 0; b < BIN_COUNT; b++) {
+    // longest rows first inside a bin, ties by vertex id
+    std::stable_sort(bins[b].begin(), bins[b].end(), [&](int32_t x, int32_t y) {
+      return d->row_ptr[x + 1] - d->row_ptr[x] > d->row_ptr[y + 1] - d->row_ptr[y];
+    });
     g->bin_begin[b] = (int64_t)all.size();
     all.insert(all.end(), bins[b].begin(), bins[b].end());
   }
@@ -371,7 +383,7 @@ void free_graph(kws_graph *g) {
   g->eng.release();
   g->prof.release();
   int32_t *ptrs[] = {g->fwd_ptr, g->fwd_col, g->rev_ptr, g->rev_col, g->inv_ptr, g->inv_vtx,
-                     g->bin_vtx, g->hub_v, g->hub_b, g->hub_e};
+                     g->lab_ptr, g->lab, g->tparent, g->bin_vtx, g->hub_v, g->hub_b, g->hub_e};
   for (int32_t *p : ptrs) dev_free(p);
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
   delete g;

@@ -8,6 +8,9 @@
 // previous finalize wrote, so the launch sequence never depends on data.
 #include <algorithm>
 
+#include <map>
+#include <mutex>
+
 #include "pass.h"
 
 namespace kws {
@@ -99,45 +102,107 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
   }
 }
 
+// ---- seeding by vertex: a block takes VB vertices at a time and gives each
+// BLOCK / VB threads; they walk the vertex's labels and (with a type
+// hierarchy) their ancestors, look each type up in the pass's keyword hash
+// and OR the lane masks of its entries into an LDS row of Wp words per
+// vertex (the threads of a vertex split the entries). The rows are then
+// written to nxt tile by tile, so the stores follow the [tile][vertex][T]
+// layout instead of scattering one word per (vertex, keyword).
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass P) {
+  extern __shared__ uint64_t s_rows[];   // [VB][Wp + 1] (one word of padding per row against bank conflicts)
+  const int64_t gid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, gsz = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
+  for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
+  for (int64_t i = gid; i < P.zero2_words; i += gsz) P.zero2[i] = 0;
+  const int tid = threadIdx.x, VB = P.seed_vb, SUB = BLOCK / VB, RS = P.Wp + 1;
+  const int vl = tid / SUB, sub = tid % SUB;
+  const uint32_t hmask = (uint32_t)P.hcap - 1;
+  for (int64_t v0 = (int64_t)blockIdx.x * VB; v0 < P.n; v0 += (int64_t)gridDim.x * VB) {
+    for (int i = tid; i < VB * RS; i += BLOCK) s_rows[i] = 0;
+    __syncthreads();
+    const int64_t v = v0 + vl;
+    if (v < P.n) {
+      uint64_t *row = s_rows + (size_t)vl * RS;
+      const int32_t a = P.lab_ptr[v], b = P.lab_ptr[v + 1];
+      for (int32_t i = a; i < b; i++) {
+        for (int32_t t = P.lab[i]; t >= 0; t = P.tparent ? P.tparent[t] : -1) {
+          uint32_t h = ((uint32_t)t * 2654435761u) & hmask;
+          int32_t key;
+          while ((key = P.h_key[h]) != t && key != -1) h = (h + 1) & hmask;
+          if (key != t) continue;
+          const int32_t e0 = P.h_beg[h], e1 = e0 + P.h_cnt[h];
+          for (int32_t e = e0 + sub; e < e1; e += SUB)
+            atomicOr((unsigned long long *)&row[P.e_word[e]], (unsigned long long)P.e_mask[e]);
+        }
+      }
+    }
+    __syncthreads();
+    const int nv = (int)min((int64_t)VB, (int64_t)P.n - v0);
+    for (int i = tid; i < P.tiles * VB * T; i += BLOCK) {
+      const int tile = i / (VB * T), r = i % (VB * T), u = r / T, w = r % T;
+      if (u >= nv) continue;
+      const uint64_t m = s_rows[(size_t)u * RS + tile * T + w];
+      if (m) P.nxt[((size_t)tile * P.n + v0 + u) * T + w] = m;
+    }
+    __syncthreads();
+  }
+}
+
 // ---- finalize one step: new = nxt & ~vis & act_new; vis |= new; distance
 // planes; next frontier buffer; nxt cleared; a frontier flag per vertex;
 // the statistics that pick the direction of the next level (frontier size,
 // its in-edges, out-edges of vertices still missing lanes), accumulated in
 // registers and reduced once per wavefront. A pure streaming pass: the
 // frontier list a push needs is built by k_compact, only for levels that push.
-template <int T>
+// T threads per vertex (one per word of a tile); each thread takes VU
+// vertices per round and loads the words of up to 8 / VU tiles of each before
+// any store, so every thread has 8 independent load pairs in flight whatever
+// the tile count (VU is 8 / min(tiles, 8), rounded to a power of two).
+template <int T, int VU>
 __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) {
   extern __shared__ uint64_t s_live[];                    // [Wp]
-  constexpr int G = T, VPB = BLOCK / T;   // T threads per vertex, one per word of a tile
-  constexpr int TG = 8;                   // tiles whose words are loaded before any store
+  constexpr int G = T, VPB = BLOCK / T;
+  constexpr int TG = 8 / VU;              // tiles per load group
   const int tid = threadIdx.x, gl = tid & (G - 1), lane = tid & 63;
   const uint64_t gmask = group_bits(lane, G);
   for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
   __syncthreads();
-  uint64_t live_acc[TG] = {0, 0, 0, 0, 0, 0, 0, 0};   // lanes with new frontier, first TG tiles
+  uint64_t live_acc[TG];                  // lanes with new frontier in the first TG tiles
+#pragma unroll
+  for (int k = 0; k < TG; k++) live_acc[k] = 0;
   uint64_t nf_acc = 0, mf_acc = 0, mu_acc = 0;
-  for (int64_t vb = (int64_t)blockIdx.x * VPB; vb < P.n; vb += (int64_t)gridDim.x * VPB) {
-    const int64_t v = vb + tid / G;
-    const bool valid = v < P.n;
-    uint64_t anyf = 0, anyneed = 0;
-    if (valid) {
-      for (int t0 = 0; t0 < P.tiles; t0 += TG) {
-        uint64_t nxv[TG], oldv[TG];
+  for (int64_t vb = (int64_t)blockIdx.x * VPB * VU; vb < P.n; vb += (int64_t)gridDim.x * VPB * VU) {
+    int64_t v[VU];
+    uint64_t anyf[VU], anyneed[VU];
+#pragma unroll
+    for (int u = 0; u < VU; u++) { v[u] = vb + u * VPB + tid / G; anyf[u] = 0; anyneed[u] = 0; }
+    for (int t0 = 0; t0 < P.tiles; t0 += TG) {
+      uint64_t nxv[VU][TG], oldv[VU][TG];
+#pragma unroll
+      for (int u = 0; u < VU; u++)
 #pragma unroll
         for (int k = 0; k < TG; k++) {
-          const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
-          nxv[k] = t0 + k < P.tiles ? P.nxt[idx] : 0ull;
-          oldv[k] = t0 + k < P.tiles ? P.vis[idx] : 0ull;
+          const bool ok = v[u] < P.n && t0 + k < P.tiles;
+          const size_t idx = ((size_t)(t0 + k) * P.n + v[u]) * T + gl;
+          nxv[u][k] = ok ? P.nxt[idx] : 0ull;
+          oldv[u][k] = ok ? P.vis[idx] : 0ull;
         }
 #pragma unroll
-        for (int k = 0; k < TG; k++) {
-          if (t0 + k >= P.tiles) break;
-          const int j = (t0 + k) * T + gl;
-          const size_t idx = ((size_t)(t0 + k) * P.n + v) * T + gl;
-          const uint64_t nx = nxv[k];
-          const int nl = S.newlvl[j];
-          const uint64_t old = nl ? oldv[k] : 0ull;
-          const uint64_t fnew = nx & ~old & S.act_new[j];
+      for (int k = 0; k < TG; k++) {
+        if (t0 + k >= P.tiles) break;
+        const int j = (t0 + k) * T + gl;
+        const int nl = S.newlvl[j];
+        const uint64_t an = S.act_new[j], ann = S.act_nn[j];
+        uint64_t lacc = 0;
+#pragma unroll
+        for (int u = 0; u < VU; u++) {
+          if (v[u] >= P.n) continue;
+          const size_t idx = ((size_t)(t0 + k) * P.n + v[u]) * T + gl;
+          const uint64_t nx = nxv[u][k];
+          const uint64_t old = nl ? oldv[u][k] : 0ull;
+          const uint64_t fnew = nx & ~old & an;
           const uint64_t nv = old | fnew;
           if (nl == 0) {
             P.vis[idx] = nv;
@@ -149,21 +214,25 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
           }
           if (S.write_next) {
             S.fr_next[idx] = fnew;
-            if (t0 + k < TG) live_acc[k] |= fnew;
-            else if (fnew) atomicOr((unsigned long long *)&s_live[j], fnew);
-            anyneed |= S.act_nn[j] & ~nv;
+            lacc |= fnew;
+            anyneed[u] |= ann & ~nv;
           }
           if (nx) P.nxt[idx] = 0;
-          anyf |= fnew;
+          anyf[u] |= fnew;
         }
+        if (t0 == 0) live_acc[k] |= lacc;
+        else if (lacc) atomicOr((unsigned long long *)&s_live[j], lacc);
       }
     }
-    const bool fflag = (__ballot(anyf != 0) & gmask) != 0;
-    const bool nflag = (__ballot(anyneed != 0) & gmask) != 0;
-    if (valid && gl == 0) {
-      if (S.build_list) S.flags_next[v] = fflag ? 1 : 0;
-      if (fflag) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
-      if (nflag) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
+#pragma unroll
+    for (int u = 0; u < VU; u++) {
+      const bool fflag = (__ballot(anyf[u] != 0) & gmask) != 0;
+      const bool nflag = (__ballot(anyneed[u] != 0) & gmask) != 0;
+      if (v[u] < P.n && gl == 0) {
+        if (S.build_list) S.flags_next[v[u]] = fflag ? 1 : 0;
+        if (fflag) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v[u] + 1] - P.rev_ptr[v[u]]); }
+        if (nflag) mu_acc += (uint64_t)(P.fwd_ptr[v[u] + 1] - P.fwd_ptr[v[u]]);
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -281,10 +350,12 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass P, const Step S, int 
 // ---- pull: a group of S = T*E threads owns one row (or one hub chunk);
 // thread (e, w) ORs word w of the frontier mask of every E-th out-neighbour.
 // Early exit once the group has found every lane the vertex still misses.
+// Rows are taken by the block in ranges [lo, hi) of the bin's (tile, row)
+// items, item = tile * n_items + row.
 template <int T, int S, bool SEG>
 __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                           int tile, int bb, int bpt) {
-  constexpr int E = S / T, GPB = BLOCK / S, U = 4;
+  constexpr int E = S / T, GPB = BLOCK / S, U = 8;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -304,12 +375,20 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
     const uint64_t need = actw & ~vis[(size_t)v * T + w];
     if ((__ballot(need != 0) & gmask) == 0) continue;
     uint64_t acc = 0;
+    // the column indices of the next round are loaded while this round's
+    // frontier words are gathered: one memory round trip per round
+    int32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int32_t e = eb + u * E + eo;
+      x[u] = e < ee ? col[e] : -1;
+    }
     for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
-      int32_t x[U];
+      int32_t xn[U];
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        const int32_t e = e0 + u * E + eo;
-        x[u] = e < ee ? col[e] : -1;
+        const int32_t e = e0 + E * U + u * E + eo;
+        xn[u] = e < ee ? col[e] : -1;
       }
       // a thread whose word has found every missing lane stops gathering
       const bool want = (acc & need) != need;
@@ -320,6 +399,8 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
 #pragma unroll
       for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
       if ((__ballot((r & need) != need) & gmask) == 0) break;
+#pragma unroll
+      for (int u = 0; u < U; u++) x[u] = xn[u];
     }
 #pragma unroll
     for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
@@ -331,9 +412,13 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
   }
 }
 
-// One launch covers every degree bin: blocks [boff[b], boff[b+1]) serve bin b
-// (b = 3 is the hub chunks), tiles x blocks-per-tile inside each range.
+// One launch covers every degree bin: blocks [boff[i], boff[i+1]) serve the
+// i-th bin of PULL_ORDER, heaviest rows first (hub chunks, large, medium,
+// small; inside a bin, rows by falling degree), so that the long rows start
+// early instead of forming the tail. Inside a bin's range: tiles x
+// blocks-per-tile, each block striding over the bin's rows.
 struct PullGrid { int32_t boff[BIN_COUNT + 2]; };
+constexpr int PULL_ORDER[BIN_COUNT + 1] = {BIN_COUNT, BIN_LARGE, BIN_MEDIUM, BIN_SMALL};
 
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, const PullGrid pg) {
@@ -341,10 +426,11 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
   constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
   const int bid = blockIdx.x;
   if (bid >= pg.boff[BIN_COUNT + 1]) return;   // the grid has one block even when every bin is empty
-  int b = 0;
-  while (b < BIN_COUNT && bid >= pg.boff[b + 1]) b++;
-  const int nblk = pg.boff[b + 1] - pg.boff[b];
-  const int bpt = nblk / P.tiles, lb = bid - pg.boff[b];
+  int i = 0;
+  while (i < BIN_COUNT && bid >= pg.boff[i + 1]) i++;
+  const int b = PULL_ORDER[i];
+  const int nblk = pg.boff[i + 1] - pg.boff[i];
+  const int bpt = nblk / P.tiles, lb = bid - pg.boff[i];
   const int tile = lb / bpt, bb = lb % bpt;
   if (tile >= P.tiles) return;
   if (b == BIN_COUNT) {
@@ -362,29 +448,46 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
 // optionally the scanned-edge count te (in-degree of every vertex each lane
 // expanded). A thread owns one vertex and holds the T words of one tile
 // (vis and distance planes) in registers; a wavefront walks the words and
-// their queries in lockstep; histogram counts are LDS atomics (the LDS unit
-// serialises equal addresses, which costs less than aggregating in code).
-template <int T>
+// their queries in lockstep. With L, the per-query table (mask, histogram
+// offset, d_max, query id, in word order), the chunk's histogram and the te
+// sums live in LDS, so the query loop issues no global load and the
+// histogram adds are LDS atomics; without L (batches too large for LDS)
+// the same loop reads the tables from global memory and adds there.
+template <int T, bool L>
 __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
   extern __shared__ uint64_t s_dyn[];
-  uint64_t *s_te = s_dyn;
-  int32_t *s_hist = (int32_t *)(s_dyn + (P.te_lds ? P.nq : 0));
+  uint64_t *s_te = s_dyn;                                   // [nq] (count_te)
+  uint64_t *s_qm = s_dyn + P.nq;                            // [nq] masks in word order
+  int32_t *s_qh = (int32_t *)(s_qm + P.nq);                 // [nq] histogram offsets
+  int32_t *s_qd = s_qh + P.nq;                              // [nq] d_max
+  int32_t *s_qx = s_qd + P.nq;                              // [nq] query ids
+  int32_t *s_wqp = s_qx + P.nq;                            // [Wp + 1] word -> first query
+  int32_t *s_hist = s_wqp + P.Wp + 1;                       // [nhist]
   const int tid = threadIdx.x, lane = tid & 63;
   const int split = (P.CH + BLOCK - 1) / BLOCK;
-  if (P.count_te && P.te_lds)
-    for (int i = tid; i < P.nq; i += BLOCK) s_te[i] = 0;
+  if (L) {
+    for (int i = tid; i <= P.Wp; i += BLOCK) s_wqp[i] = P.word_q_ptr[i];
+    for (int i = tid; i < P.nq; i += BLOCK) {
+      const int q = P.word_q[i];
+      s_te[i] = 0;
+      s_qm[i] = P.q_mask[q];
+      s_qh[i] = P.q_hoff[q];
+      s_qd[i] = P.q_dmax[q];
+      s_qx[i] = q;
+    }
+  }
   for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
     const int c = (int)(bid / split), part = (int)(bid % split);
-    if (P.hist_lds)
+    if (L)
       for (int i = tid; i < P.nhist; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
-    int32_t *hist = P.hist_lds ? s_hist : P.hist + (size_t)c * P.nhist;
     const int64_t cend = min((int64_t)P.n, (int64_t)(c + 1) * P.CH);
     const int64_t v = (int64_t)c * P.CH + (int64_t)part * BLOCK + tid;
     const bool valid = v < cend;
     const uint64_t indeg = (valid && P.count_te) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
+    const int32_t *wqp = L ? s_wqp : P.word_q_ptr;
     for (int tile = 0; tile < P.tiles; tile++) {
-      if (P.word_q_ptr[tile * T] == P.word_q_ptr[(tile + 1) * T]) continue;   // no query in this tile
+      if (wqp[tile * T] == wqp[(tile + 1) * T]) continue;   // no query in this tile
       const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T;
       uint64_t vis[T], pl[4][T];
 #pragma unroll
@@ -396,13 +499,15 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
 #pragma unroll
       for (int w = 0; w < T; w++) {
         const int j = tile * T + w;
-        const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
+        const int qb = wqp[j], qe = wqp[j + 1];
         if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
         for (int qi = qb; qi < qe; qi++) {
-          const int q = P.word_q[qi];
-          const uint64_t m = P.q_mask[q], x = vis[w] & m;
+          const uint64_t m = L ? s_qm[qi] : P.q_mask[P.word_q[qi]];
+          const bool root = valid && (m & ~vis[w]) == 0;
           if (P.count_te) {
-            const int dq = P.q_dmax[q];
+            const int q = L ? s_qx[qi] : P.word_q[qi];
+            const int dq = L ? s_qd[qi] : P.q_dmax[q];
+            const uint64_t x = vis[w] & m;
             uint64_t eq = x;
 #pragma unroll
             for (int b = 0; b < 4; b++)
@@ -411,29 +516,33 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
             if (__ballot(t != 0)) {
               for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
               if (lane == 0) {
-                if (P.te_lds) atomicAdd((unsigned long long *)&s_te[q], (unsigned long long)t);
+                if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
                 else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
               }
             }
           }
-          const bool root = x == m && valid;
-          int sc = 0;
+          if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
+          int sc = __popcll(pl[0][w] & m);
 #pragma unroll
-          for (int b = 0; b < 4; b++) sc += __popcll(pl[b][w] & m) << b;   // planes past B are zero
-          if (root) atomicAdd(&hist[P.q_hoff[q] + sc], 1);
+          for (int b = 1; b < 4; b++)
+            if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
+          if (root) {
+            if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
+            else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
+          }
         }
       }
     }
     __syncthreads();
-    if (P.hist_lds)
+    if (L)
       for (int i = tid; i < P.nhist; i += BLOCK)
         if (s_hist[i]) atomicAdd(&P.hist[(size_t)c * P.nhist + i], s_hist[i]);
     __syncthreads();
   }
-  if (P.count_te && P.te_lds) {
+  if (L && P.count_te) {
     __syncthreads();
     for (int i = tid; i < P.nq; i += BLOCK)
-      if (s_te[i]) atomicAdd((unsigned long long *)&P.te[i], (unsigned long long)s_te[i]);
+      if (s_te[i]) atomicAdd((unsigned long long *)&P.te[s_qx[i]], (unsigned long long)s_te[i]);
   }
 }
 
@@ -724,6 +833,25 @@ inline unsigned clamp_grid(int64_t blocks) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 1 << 16));
 }
 
+// Blocks of BLOCK threads that the whole device holds at once for this
+// kernel and dynamic LDS size (occupancy x compute units), cached per kernel
+// and LDS size.
+int64_t resident_blocks(const void *fn, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void *, size_t>, int64_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({fn, lds});
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  int64_t r = 1024;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, lds) == hipSuccess && per_cu > 0 && cus > 0)
+    r = (int64_t)per_cu * cus;
+  cache[{fn, lds}] = r;
+  return r;
+}
+
 kws_status launch_check(const char *what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(KWS_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
@@ -756,11 +884,12 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
   PullGrid pg;
   const int sizes[BIN_COUNT + 1] = {S_SMALL, S_MED, 64, 64};
   pg.boff[0] = 0;
-  for (int b = 0; b <= BIN_COUNT; b++) {
+  for (int i = 0; i <= BIN_COUNT; i++) {
+    const int b = PULL_ORDER[i];
     const int64_t items = b < BIN_COUNT ? P.bin_begin[b + 1] - P.bin_begin[b] : P.n_hub;
     const int64_t gpb = BLOCK / sizes[b];
     const int64_t bpt = items ? std::min<int64_t>((items + gpb - 1) / gpb, 16384 / P.tiles + 1) : 0;
-    pg.boff[b + 1] = pg.boff[b] + (int32_t)(bpt * P.tiles);
+    pg.boff[i + 1] = pg.boff[i] + (int32_t)(bpt * P.tiles);
   }
   {
     Timer t(prof, s, KC_PULL);
@@ -771,10 +900,23 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
 
 template <int T>
 kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
-  const unsigned grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + BLOCK / T - 1) / (BLOCK / T), 1024));
+  const int vu = P.tiles >= 8 ? 1 : P.tiles >= 4 ? 2 : P.tiles >= 2 ? 4 : 8;
+  const int64_t per_block = (int64_t)(BLOCK / T) * vu;
+  const size_t lds = sizeof(uint64_t) * (size_t)P.Wp;
+  // one round of resident blocks that stride over the vertices: a second,
+  // partial round of blocks would leave most of the chip idle at its end
+  auto grid_for_kernel = [&](const void *fn) {
+    const int64_t want = ((int64_t)P.n + per_block - 1) / per_block;
+    return clamp_grid(std::min<int64_t>(want, resident_blocks(fn, lds)));
+  };
   {
     Timer t(prof, s, KC_FINALIZE);
-    k_finalize<T><<<grid, BLOCK, sizeof(uint64_t) * (size_t)P.Wp, s>>>(P, S);
+    switch (vu) {
+      case 1: k_finalize<T, 1><<<grid_for_kernel((const void *)k_finalize<T, 1>), BLOCK, lds, s>>>(P, S); break;
+      case 2: k_finalize<T, 2><<<grid_for_kernel((const void *)k_finalize<T, 2>), BLOCK, lds, s>>>(P, S); break;
+      case 4: k_finalize<T, 4><<<grid_for_kernel((const void *)k_finalize<T, 4>), BLOCK, lds, s>>>(P, S); break;
+      default: k_finalize<T, 8><<<grid_for_kernel((const void *)k_finalize<T, 8>), BLOCK, lds, s>>>(P, S); break;
+    }
   }
   return launch_check("finalize");
 }
@@ -784,9 +926,13 @@ kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
   if (P.nq == 0) return KWS_OK;
   {
     Timer t(prof, s, KC_SCORE);
-    const size_t lds = (P.te_lds ? sizeof(uint64_t) * P.nq : 0) + (P.hist_lds ? sizeof(int32_t) * P.nhist : 0);
     const int64_t split = (P.CH + BLOCK - 1) / BLOCK;
-    k_score<T><<<clamp_grid(P.chunks * split), BLOCK, lds, s>>>(P);
+    if (P.hist_lds) {
+      const size_t lds = (size_t)P.nq * (8 + 8 + 4 + 4 + 4) + sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist);
+      k_score<T, true><<<clamp_grid(P.chunks * split), BLOCK, lds, s>>>(P);
+    } else {
+      k_score<T, false><<<clamp_grid(P.chunks * split), BLOCK, 0, s>>>(P);
+    }
   }
   KWS_TRY(launch_check("score"));
   {
@@ -826,8 +972,24 @@ kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
 }  // namespace
 
 kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
-  const int64_t items =
-      std::max<int64_t>(P.total_seeds, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
+  const int64_t items = std::max<int64_t>(P.seed_by_vertex ? P.n : P.total_seeds,
+                                          std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
+  if (P.seed_by_vertex) {
+    Timer t(prof, s, KC_SEED);
+    const int64_t vblocks = ((int64_t)P.n + P.seed_vb - 1) / P.seed_vb;
+    const int64_t zblocks = (std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)) + BLOCK - 1) / BLOCK;
+    const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(std::min<int64_t>(vblocks, 4096), zblocks), 65535));
+    const size_t lds = sizeof(uint64_t) * (size_t)P.seed_vb * (size_t)(P.Wp + 1);
+    switch (P.T) {
+      case 1: k_seed_vertex<1><<<grid, BLOCK, lds, s>>>(P); break;
+      case 2: k_seed_vertex<2><<<grid, BLOCK, lds, s>>>(P); break;
+      case 4: k_seed_vertex<4><<<grid, BLOCK, lds, s>>>(P); break;
+      case 8: k_seed_vertex<8><<<grid, BLOCK, lds, s>>>(P); break;
+      case 16: k_seed_vertex<16><<<grid, BLOCK, lds, s>>>(P); break;
+      default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
+    }
+    return launch_check("seed");
+  }
   {
     Timer t(prof, s, KC_SEED);
     switch (P.T) {

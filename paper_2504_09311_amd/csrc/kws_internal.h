@@ -81,8 +81,8 @@ struct Profiler {
 enum { BIN_SMALL = 0, BIN_MEDIUM, BIN_LARGE, BIN_COUNT };
 constexpr int32_t BIN_SMALL_MAX = 8;
 constexpr int32_t BIN_MEDIUM_MAX = 128;
-constexpr int32_t BIN_LARGE_MAX = 4096;
-constexpr int32_t HUB_CHUNK = 4096;
+constexpr int32_t BIN_LARGE_MAX = 1024;
+constexpr int32_t HUB_CHUNK = 1024;
 
 constexpr int MAX_WORDS = 1024;      // words per device pass (65536 lanes)
 constexpr int STAT_STRIPES = 32;     // frontier statistics: stripes of STAT_STRIDE words
@@ -126,6 +126,8 @@ struct kws_graph {
   int32_t *fwd_ptr = nullptr, *fwd_col = nullptr;
   int32_t *rev_ptr = nullptr, *rev_col = nullptr;
   int32_t *inv_ptr = nullptr, *inv_vtx = nullptr;    // by preorder key
+  int32_t *lab_ptr = nullptr, *lab = nullptr;        // vertex labels (seeding by vertex)
+  int32_t *tparent = nullptr;                        // type parents, or null for flat labels
   int32_t *bin_vtx = nullptr;                        // vertices of the pull bins
   int32_t *hub_v = nullptr, *hub_b = nullptr, *hub_e = nullptr;
   int64_t bin_begin[kws::BIN_COUNT + 1] = {};
@@ -133,6 +135,8 @@ struct kws_graph {
   // host mirrors used for planning
   std::vector<int32_t> pre, span;                    // type preorder key and subtree size
   std::vector<int32_t> h_inv_ptr;                    // [n_labels + 1]
+  int64_t h_lab_total = 0;                           // number of (vertex, label) pairs
+  int32_t type_depth = 0;                            // longest parent chain (0 for flat labels)
   int32_t max_out = 0, max_in = 0;
   int64_t device_bytes = 0;
   // execution

@@ -32,7 +32,13 @@ struct Pass {
   // state
   uint64_t *vis, *fr0, *fr1, *nxt, *planes;
   int32_t *flist, *flist_eoff;
-  // lanes to seed
+  // lanes to seed: by scattering over inverted-index slices, or (seed_by_vertex)
+  // by every vertex looking its labels and their type ancestors up in a hash
+  // of keyword -> [(word, lane mask)] entries
+  int32_t seed_by_vertex, seed_vb, hcap;   // seed_vb: vertices per block round (power of two <= BLOCK)
+  const int32_t *lab_ptr, *lab, *tparent;
+  const int32_t *h_key, *h_beg, *h_cnt, *e_word;
+  const uint64_t *e_mask;
   const int64_t *lane_seed_off;      // [n_lanes + 1]
   const int32_t *lane_seed_begin;    // [n_lanes]
   const int32_t *lane_word, *lane_bit;

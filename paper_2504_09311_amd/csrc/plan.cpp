@@ -100,6 +100,36 @@ void LaneTables::add(const kws_graph *g, const LaneInfo &li) {
   seed_off.push_back(seed_off.back() + (e - b));
   word.push_back(li.word);
   bit.push_back(li.bit);
+  kw.push_back(li.kw);
+}
+
+// Open-addressing table keyword -> entries [(word, lane mask)], one entry
+// per word that holds lanes of the keyword; probing is linear from
+// (kw * 2654435761) mod capacity, capacity a power of two >= 2 * keywords.
+void LaneTables::build_hash() {
+  std::unordered_map<int32_t, std::vector<std::pair<int32_t, uint64_t>>> by_kw;
+  for (int l = 0; l < n(); l++) {
+    auto &v = by_kw[kw[l]];
+    bool found = false;
+    for (auto &wm : v)
+      if (wm.first == word[l]) { wm.second |= 1ull << bit[l]; found = true; break; }
+    if (!found) v.push_back({word[l], 1ull << bit[l]});
+  }
+  int32_t cap = 16;
+  while (cap < 2 * (int32_t)by_kw.size()) cap <<= 1;
+  h_key.assign(cap, -1);
+  h_beg.assign(cap, 0);
+  h_cnt.assign(cap, 0);
+  e_word.clear();
+  e_mask.clear();
+  for (auto &kv : by_kw) {
+    uint32_t h = ((uint32_t)kv.first * 2654435761u) & (uint32_t)(cap - 1);
+    while (h_key[h] != -1) h = (h + 1) & (uint32_t)(cap - 1);
+    h_key[h] = kv.first;
+    h_beg[h] = (int32_t)e_word.size();
+    h_cnt[h] = (int32_t)kv.second.size();
+    for (auto &wm : kv.second) { e_word.push_back(wm.first); e_mask.push_back(wm.second); }
+  }
 }
 
 kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *> &qs,
@@ -153,8 +183,10 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
                                                                               std::min<int64_t>(512, ((int64_t)n + 2047) / 2048))));
   CH = (int)align_up((size_t)((n + chunks - 1) / chunks), 64);
   chunks = (n + CH - 1) / CH;
-  hist_lds = nhist <= 16384;
-  te_lds = nq <= 2048;
+  // the score step keeps the query table (28 bytes per query), the word ->
+  // query offsets and one chunk's histogram in at most 64 KB of LDS
+  hist_lds = (size_t)nq * 28 + ((size_t)Wp + 1 + (size_t)nhist) * 4 <= 65536;
+  te_lds = hist_lds;
   if ((size_t)chunks * (size_t)nhist > (size_t)INT32_MAX) return fail(KWS_EOVERFLOW, "histogram too large");
   return KWS_OK;
 }
@@ -201,12 +233,18 @@ QueryOffsets add_query_tables(PlanWriter &pw, const QueryTables &Q) {
   return o;
 }
 
-LaneOffsets add_lane_tables(PlanWriter &pw, const LaneTables &L) {
+LaneOffsets add_lane_tables(PlanWriter &pw, LaneTables &L) {
+  L.build_hash();
   LaneOffsets o;
   o.seed_off = pw.add(L.seed_off.data(), L.seed_off.size() * 8);
   o.seed_begin = pw.add(L.seed_begin.data(), L.seed_begin.size() * 4);
   o.word = pw.add(L.word.data(), L.word.size() * 4);
   o.bit = pw.add(L.bit.data(), L.bit.size() * 4);
+  o.h_key = pw.add(L.h_key.data(), L.h_key.size() * 4);
+  o.h_beg = pw.add(L.h_beg.data(), L.h_beg.size() * 4);
+  o.h_cnt = pw.add(L.h_cnt.data(), L.h_cnt.size() * 4);
+  o.e_word = pw.add(L.e_word.data(), L.e_word.size() * 4);
+  o.e_mask = pw.add(L.e_mask.data(), L.e_mask.size() * 8);
   return o;
 }
 
@@ -267,6 +305,25 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.lane_seed_begin = (const int32_t *)(dp + lo.seed_begin);
   P.lane_word = (const int32_t *)(dp + lo.word);
   P.lane_bit = (const int32_t *)(dp + lo.bit);
+  P.hcap = (int32_t)L.h_key.size();
+  P.h_key = (const int32_t *)(dp + lo.h_key);
+  P.h_beg = (const int32_t *)(dp + lo.h_beg);
+  P.h_cnt = (const int32_t *)(dp + lo.h_cnt);
+  P.e_word = (const int32_t *)(dp + lo.e_word);
+  P.e_mask = (const uint64_t *)(dp + lo.e_mask);
+  P.lab_ptr = g->lab_ptr;
+  P.lab = g->lab;
+  P.tparent = g->tparent;
+  // seed by vertex when scattering would cost more random atomics than one
+  // pass over the vertices and their labels
+  const int64_t lab_total = g->h_lab_total;
+  const int mode = g->opt.seed_mode;
+  P.seed_by_vertex = L.n() > 0 && (mode == 2 || (mode == 0 && P.total_seeds > (int64_t)g->n + lab_total * (1 + g->type_depth)));
+  if (P.seed_by_vertex) P.total_seeds = 0;
+  // vertices per block round of the vertex seeding: rows of Wp + 1 words in
+  // at most 64 KB of LDS
+  P.seed_vb = BLOCK;
+  while (P.seed_vb > 1 && (size_t)P.seed_vb * (size_t)(P.Wp + 1) * 8 > 65536) P.seed_vb >>= 1;
   P.q_mask = (const uint64_t *)(dp + qo.mask);
   P.q_word = (const int32_t *)(dp + qo.word);
   P.q_dmax = (const int32_t *)(dp + qo.dmax);

@@ -60,7 +60,7 @@ class BatchResultC(C.Structure):
 class Options(C.Structure):
     _fields_ = [("direction", C.c_int32), ("alpha", C.c_float), ("tile_words", C.c_int32),
                 ("block", C.c_int32), ("use_graph", C.c_int32), ("share_lanes", C.c_int32),
-                ("count_te", C.c_int32)]
+                ("count_te", C.c_int32), ("seed_mode", C.c_int32)]
 
 
 class TuneReport(C.Structure):
@@ -330,9 +330,9 @@ class Graph:
 
     # ---- configuration and introspection
     def set_options(self, direction: int = 0, alpha: float = 0.0, tile_words: int = 0, use_graph: int = 0,
-                    share_lanes: int = 0, count_te: int = 1):
+                    share_lanes: int = 0, count_te: int = 1, seed_mode: int = 0):
         """Engine options (kws_set_options). count_te defaults to on here, as tests compare it."""
-        o = Options(direction, alpha, tile_words, 0, use_graph, share_lanes, count_te)
+        o = Options(direction, alpha, tile_words, 0, use_graph, share_lanes, count_te, seed_mode)
         _check(self._lib.kws_set_options(self.h, C.byref(o)))
 
     def autotune(self, queries, reps: int = 3, budget_ms: float = 0.0, cache_path: Optional[str] = None):

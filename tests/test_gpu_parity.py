@@ -68,7 +68,7 @@ def test_tiny_random(K, block):
             assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"tiny {seed} plain {i}")
         for direction in (0, 1, 2):
             G.set_options(direction=direction, tile_words=[1, 2, 4, 8, 16][seed % 5],
-                          share_lanes=1 if seed % 2 else -1)
+                          share_lanes=1 if seed % 2 else -1, seed_mode=(seed + direction) % 3)
             assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction}")
         assert_all_same(G.search_batch_each(qs), want, f"tiny {seed} batch (per-query results)")
         G.close()
@@ -87,9 +87,10 @@ def test_tiny_batch_of_many_words(K):
     G = K.Graph.from_synth(g)
     for tw in (1, 4, 16):
         for share in (1, -1):
-            say("many words", tw, share)
-            G.set_options(tile_words=tw, share_lanes=share)
-            assert_all_same(G.search_batch(qs), want, f"many tw {tw} share {share}")
+            for sm in (1, 2):
+                say("many words", tw, share, sm)
+                G.set_options(tile_words=tw, share_lanes=share, seed_mode=sm)
+                assert_all_same(G.search_batch(qs), want, f"many tw {tw} share {share} seed {sm}")
     G.close()
 
 
@@ -137,15 +138,28 @@ def test_chunglu10k_mixed_shapes(K, chunglu):
     G.set_options()
 
 
+def test_chunglu10k_large_batch(K, chunglu):
+    # 2400 queries: the score step's query table no longer fits in LDS, so
+    # the global-memory variant runs
+    g, o, G = chunglu
+    from synth import gen
+    qs = gen.queries(2400, 500, 1.1, 1, 6, [1, 2, 3], 10, 0x5EED0101, 77)
+    want = oracle_results(o, qs)
+    say("chunglu large batch")
+    assert_all_same(G.search_batch(qs), want, "chunglu 2400 queries")
+
+
 def test_distances_export_certificate(K, chunglu):
     g, o, G = chunglu
     for t in (0, 1, 17, 250, 499):
         for d_max in (0, 2, 5):
             say("export", t, d_max)
+            G.set_options(seed_mode=1 + (t + d_max) % 2)
             d = G.debug_distances(t, d_max)
             want, _ = o.distances(t, d_max)
             assert np.array_equal(d, want)
             assert brute.certificate(g.row_ptr, g.col, o.keyword_set(t), d, d_max) == []
+    G.set_options()
 
 
 @pytest.fixture(scope="module")
@@ -165,6 +179,9 @@ def test_rmat14_options_grid(K, rmat14):
             assert_all_same(G.search_batch(qs), want, f"rmat14 tw {tw} dir {direction}")
     G.set_options(share_lanes=-1)
     assert_all_same(G.search_batch(qs), want, "rmat14 no sharing")
+    for sm in (1, 2):
+        G.set_options(seed_mode=sm, tile_words=4)
+        assert_all_same(G.search_batch(qs), want, f"rmat14 seed mode {sm}")
     G.set_options()
     for i in range(0, 96, 7):
         assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"rmat14 plain {i}")
@@ -177,9 +194,11 @@ def test_rmat14_hierarchy(K):
     want = oracle_results(o, qs)
     G = K.Graph.from_synth(g)
     for direction in (0, 1, 2):
-        say("rmat14 hier", direction)
-        G.set_options(direction=direction)
-        assert_all_same(G.search_batch(qs), want, f"hier dir {direction}")
+        for sm in (0, 1, 2):
+            say("rmat14 hier", direction, sm)
+            G.set_options(direction=direction, seed_mode=sm)
+            assert_all_same(G.search_batch(qs), want, f"hier dir {direction} seed {sm}")
+    G.set_options()
     for i in range(0, 64, 9):
         assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"hier plain {i}")
     G.close()
