@@ -88,6 +88,27 @@ def byte_model(st: dict, n: int, kernel: str) -> float:
     return 0.0
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when there is none or
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        line = line.strip().strip("`")
+        if ":" in line:
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2504_09311_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernels_hip_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
+
+
 def cpu_baseline(g, qs, budget_s: float):
     import oracle
     o = oracle.Oracle(g)
@@ -266,10 +287,15 @@ def main():
             per_launch_bytes = modeled[dom] * args.steps / launches
             avg_s = kernels[dom]["total_ms"] / 1e3 / launches
             achieved = per_launch_bytes / avg_s / 1e9
+            traffic = measured_traffic(dom, args.workload)
             roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                            frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                            frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                             bytes_per_launch=int(per_launch_bytes), avg_launch_us=round(avg_s * 1e6, 3),
                             launches=launches)
+            if traffic:
+                roofline["traffic_gbs"] = round(traffic / avg_s / 1e9, 2)
+                roofline["traffic_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+                roofline["waste_ratio"] = round(traffic / per_launch_bytes, 3)
 
     # ---- plain path: one query per call, same queries
     plain = None

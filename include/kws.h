@@ -163,7 +163,8 @@ kws_status kws_debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t 
 typedef struct {
   int32_t direction;     /* 0 auto (device-side choice), 1 always push, 2 always pull */
   float alpha;           /* pull when alpha * frontier_in_edges > unfinished_out_edges */
-  int32_t tile_words;    /* words per vertex per tile: 1, 2, 4, 8 or 16 */
+  int32_t tile_words;    /* widest tile to use, in words per vertex: 1, 2, 4, 8 or 16 (default 16);
+                            a batch takes the tile width its cost model prefers up to this */
   int32_t block;         /* threads per workgroup for the streaming kernels: 64..1024 */
   int32_t use_graph;     /* 1: capture each batch shape once in a hipGraph and replay it */
   int32_t share_lanes;   /* 1 (default): queries in one word share equal (keyword, d_max) lanes; -1: off */
@@ -265,7 +266,8 @@ typedef struct {
   int32_t max_words;       /* word slots; 0 = as many as mem_bytes allows (at most 1024) */
   int32_t max_dmax;        /* largest d_max accepted (sizes the distance planes); 0 = 15 */
   int32_t queue_capacity;  /* waiting queries before submit returns KWS_EBUSY; 0 = 65536 */
-  int32_t tile_words;      /* words per vertex per tile (1, 2, 4, 8, 16); 0 = 8 */
+  int32_t tile_words;      /* words per vertex per tile (1, 2, 4, 8, 16); 0 = the smallest power of
+                              two covering the word slots, at most 16 */
   int64_t mem_bytes;       /* device bytes for the search state; 0 = the graph's budget */
 } kws_server_opts;
 kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_server **out);

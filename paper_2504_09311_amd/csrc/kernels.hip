@@ -486,49 +486,53 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
     const bool valid = v < cend;
     const uint64_t indeg = (valid && P.count_te) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
     const int32_t *wqp = L ? s_wqp : P.word_q_ptr;
+    constexpr int H = T < 8 ? T : 8;      // words held in registers at a time
     for (int tile = 0; tile < P.tiles; tile++) {
-      if (wqp[tile * T] == wqp[(tile + 1) * T]) continue;   // no query in this tile
-      const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T;
-      uint64_t vis[T], pl[4][T];
+#pragma unroll 1
+      for (int h0 = 0; h0 < T; h0 += H) {
+        if (wqp[tile * T + h0] == wqp[tile * T + h0 + H]) continue;   // no query in these words
+        const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T + h0;
+        uint64_t vis[H], pl[4][H];
 #pragma unroll
-      for (int w = 0; w < T; w++) vis[w] = valid ? P.vis[base + w] : 0ull;
+        for (int w = 0; w < H; w++) vis[w] = valid ? P.vis[base + w] : 0ull;
 #pragma unroll
-      for (int b = 0; b < 4; b++)
+        for (int b = 0; b < 4; b++)
 #pragma unroll
-        for (int w = 0; w < T; w++) pl[b][w] = (valid && b < P.B) ? P.planes[b * P.pstride + base + w] : 0ull;
+          for (int w = 0; w < H; w++) pl[b][w] = (valid && b < P.B) ? P.planes[b * P.pstride + base + w] : 0ull;
 #pragma unroll
-      for (int w = 0; w < T; w++) {
-        const int j = tile * T + w;
-        const int qb = wqp[j], qe = wqp[j + 1];
-        if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
-        for (int qi = qb; qi < qe; qi++) {
-          const uint64_t m = L ? s_qm[qi] : P.q_mask[P.word_q[qi]];
-          const bool root = valid && (m & ~vis[w]) == 0;
-          if (P.count_te) {
-            const int q = L ? s_qx[qi] : P.word_q[qi];
-            const int dq = L ? s_qd[qi] : P.q_dmax[q];
-            const uint64_t x = vis[w] & m;
-            uint64_t eq = x;
+        for (int w = 0; w < H; w++) {
+          const int j = tile * T + h0 + w;
+          const int qb = wqp[j], qe = wqp[j + 1];
+          if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
+          for (int qi = qb; qi < qe; qi++) {
+            const uint64_t m = L ? s_qm[qi] : P.q_mask[P.word_q[qi]];
+            const bool root = valid && (m & ~vis[w]) == 0;
+            if (P.count_te) {
+              const int q = L ? s_qx[qi] : P.word_q[qi];
+              const int dq = L ? s_qd[qi] : P.q_dmax[q];
+              const uint64_t x = vis[w] & m;
+              uint64_t eq = x;
 #pragma unroll
-            for (int b = 0; b < 4; b++)
-              if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
-            uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
-            if (__ballot(t != 0)) {
-              for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-              if (lane == 0) {
-                if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
-                else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
+              for (int b = 0; b < 4; b++)
+                if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
+              uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
+              if (__ballot(t != 0)) {
+                for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+                if (lane == 0) {
+                  if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
+                  else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
+                }
               }
             }
-          }
-          if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
-          int sc = __popcll(pl[0][w] & m);
+            if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
+            int sc = __popcll(pl[0][w] & m);
 #pragma unroll
-          for (int b = 1; b < 4; b++)
-            if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
-          if (root) {
-            if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
-            else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
+            for (int b = 1; b < 4; b++)
+              if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
+            if (root) {
+              if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
+              else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
+            }
           }
         }
       }
@@ -609,12 +613,17 @@ __device__ __forceinline__ int lane_dist(const Pass &P, size_t idx, int bit) {
 }
 
 // ---- select: scan one chunk for one query in vertex order; keep every root
-// below s* and the first `need` ties overall (ranked across chunks).
+// below s* and the first `need` ties overall (ranked across chunks). One
+// wavefront per work item: ranks by ballot prefix counts (no block
+// barriers), and the vis words of SU rounds of 64 vertices are loaded before
+// any is used.
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_select(const Pass P) {
-  const int tid = threadIdx.x;
+  constexpr int WAVES = BLOCK / 64, SU = 4;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
   const int n_items = *P.work_cnt;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  for (int it = blockIdx.x * WAVES + wid; it < n_items; it += gridDim.x * WAVES) {
     const int4 wk = P.work[it];
     const int q = wk.x, c = wk.y, lt_c = wk.w;
     const int32_t sstar = P.qsel[q * 4 + 1], need = P.qsel[q * 4 + 2];
@@ -624,30 +633,33 @@ __global__ __launch_bounds__(BLOCK) void k_select(const Pass P) {
     const int w = word % T;
     int32_t ties = wk.z, lts = 0;
     const int64_t v0 = (int64_t)c * P.CH, v1 = min((int64_t)P.n, v0 + P.CH);
-    for (int64_t vb = v0; vb < v1; vb += BLOCK) {
-      const int64_t v = vb + tid;
-      bool lt = false, tie = false;
-      int s = 0;
-      if (v < v1) {
-        const size_t idx = tb + (size_t)v * T + w;
-        if ((P.vis[idx] & m) == m) {
+    for (int64_t vb = v0; vb < v1 && !(lts >= lt_c && ties >= need); vb += 64 * SU) {
+      uint64_t vw[SU];
+#pragma unroll
+      for (int u = 0; u < SU; u++) {
+        const int64_t v = vb + u * 64 + lane;
+        vw[u] = v < v1 ? P.vis[tb + (size_t)v * T + w] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < SU; u++) {
+        const int64_t v = vb + u * 64 + lane;
+        const bool root = v < v1 && (vw[u] & m) == m;
+        int s = 0;
+        if (root) {
+          const size_t idx = tb + (size_t)v * T + w;
           for (int b = 0; b < P.B; b++) s += __popcll(P.planes[b * P.pstride + idx] & m) << b;
-          lt = s < sstar;
-          tie = s == sstar;
         }
+        const bool lt = root && s < sstar, tie = root && s == sstar;
+        const uint64_t tb_mask = __ballot(tie), lt_mask = __ballot(lt);
+        const int32_t rank = ties + __popcll(tb_mask & below);
+        if (lt || (tie && rank < need)) {
+          const int32_t pos = atomicAdd(&P.cand_cnt[q], 1);
+          P.cand[P.q_coff[q] + pos] = ((uint64_t)(uint32_t)s << 32) | (uint64_t)(uint32_t)v;
+        }
+        ties += __popcll(tb_mask);
+        lts += __popcll(lt_mask);
       }
-      int32_t ntie, nlt;
-      const int32_t rank = block_scan(tie ? 1 : 0, &ntie) + ties;
-      block_scan(lt ? 1 : 0, &nlt);
-      if (lt || (tie && rank < need)) {
-        const int32_t pos = atomicAdd(&P.cand_cnt[q], 1);
-        P.cand[P.q_coff[q] + pos] = ((uint64_t)(uint32_t)s << 32) | (uint64_t)(uint32_t)v;
-      }
-      ties += ntie;
-      lts += nlt;
-      if (lts >= lt_c && ties >= need) break;
     }
-    __syncthreads();
   }
 }
 

@@ -444,14 +444,18 @@ kws_status ensure_state(Engine &E, size_t words_per_array, hipStream_t s) {
   return KWS_OK;
 }
 
-// Pull gathers one 8T-byte piece per edge and tile (at least a 64-byte
-// line); the streaming kernels touch every padded word of every vertex.
+// Widest useful tile up to max_tile: pull gathers one 8T-byte piece per edge
+// and tile, and a miss moves a whole 128-byte line; the streaming kernels
+// touch every padded word of every vertex.
 int choose_tile(int W, int max_tile, int64_t n, int64_t m) {
   int T = 1;
   double best = 0;
   for (int t = 1; t <= std::max(1, max_tile); t <<= 1) {
     const double tl = (W + t - 1) / t;
-    const double cost = (double)m * tl * (4.0 + std::max(8.0 * t, 64.0)) + (double)n * tl * t * 8.0 * 3.0 * 2.0;
+    // an edge gathered in a tile costs its column index plus at least one
+    // 128-byte cache line of frontier words; every tile word costs about
+    // 48 bytes of streaming per vertex (finalize and score)
+    const double cost = (double)m * tl * (4.0 + std::max(8.0 * t, 128.0)) + (double)n * tl * t * 8.0 * 3.0 * 2.0;
     if (t == 1 || cost <= best) { best = cost; T = t; }
   }
   return T;

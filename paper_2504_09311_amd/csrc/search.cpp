@@ -197,7 +197,7 @@ void default_options(kws_options *o) {
   std::memset(o, 0, sizeof(*o));
   o->direction = 0;
   o->alpha = 8.0f;
-  o->tile_words = 8;
+  o->tile_words = 16;
   o->block = BLOCK;
   o->use_graph = 0;
   o->share_lanes = 1;

@@ -325,8 +325,7 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   if (o.max_dmax == 0) o.max_dmax = KWS_MAX_DMAX;
   if (o.queue_capacity < 0 || o.max_words < 0 || o.mem_bytes < 0) return kws::fail(KWS_EINVAL, "negative option");
   if (o.queue_capacity == 0) o.queue_capacity = 65536;
-  if (o.tile_words == 0) o.tile_words = 8;
-  if (o.tile_words != 1 && o.tile_words != 2 && o.tile_words != 4 && o.tile_words != 8 && o.tile_words != 16)
+  if (o.tile_words != 0 && o.tile_words != 1 && o.tile_words != 2 && o.tile_words != 4 && o.tile_words != 8 && o.tile_words != 16)
     return kws::fail(KWS_EINVAL, "tile_words must be 1, 2, 4, 8 or 16");
   int B = 0;
   while ((1 << B) <= o.max_dmax) B++;
@@ -336,6 +335,9 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   if (o.max_words) words = std::min(words, o.max_words);
   if (words < 1) return kws::fail(KWS_ENOMEM, "memory budget holds no word slot (%zu bytes per slot)", per_word);
   o.max_words = words;
+  // default tile: as wide as the slots allow, up to one 128-byte line of
+  // words per vertex (a pull gather moves a whole line)
+  if (o.tile_words == 0) o.tile_words = words >= 16 ? 16 : words > 4 ? 8 : words > 2 ? 4 : words > 1 ? 2 : 1;
   kws_server *s = new kws_server();
   s->g = g;
   s->opt = o;
