@@ -222,7 +222,10 @@ kws_status kws_graph_info_get(kws_graph *g, kws_graph_info *info);
 /* Per-kernel timing with HIP events on the handle's stream. While enabled
  * each launch is bracketed by events; kws_profile_read returns, for kernel
  * class id, the number of launches and their summed duration (ms) since
- * the last reset. kws_profile_name gives the class name (NULL past the end). */
+ * the last reset. kws_profile_name gives the class name (NULL past the end).
+ * The classes named host_plan, host_launch, host_wait and host_collect are
+ * host wall time per batch pass: planning and plan upload, kernel enqueue,
+ * waiting for the device, unpacking the results. */
 kws_status kws_profile_enable(kws_graph *g, int32_t on);
 kws_status kws_profile_reset(kws_graph *g);
 kws_status kws_profile_read(kws_graph *g, int32_t id, int64_t *launches, double *total_ms);

@@ -129,8 +129,9 @@ void Engine::release() {
 
 // ---------------------------------------------------------------- profiler
 const char *kernel_class_name(int id) {
-  static const char *names[KC_COUNT] = {"seed", "push", "pull", "finalize", "score", "threshold",
-                                        "select", "finish", "answer", "export", "build"};
+  static const char *names[KC_COUNT] = {"seed",   "push",      "pull",        "finalize",    "score",
+                                        "threshold", "select", "finish",    "answer",      "export",
+                                        "build",  "host_plan", "host_launch", "host_wait", "host_collect"};
   return id >= 0 && id < KC_COUNT ? names[id] : nullptr;
 }
 

@@ -336,7 +336,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass P, const Step S, int 
     while (j + 1 < nf && P.flist_eoff[j + 1] <= e) j++;
     const int32_t v = P.flist[j];
     const int32_t p = P.rev_col[P.rev_ptr[v] + (int32_t)(e - P.flist_eoff[j])];
-    for (int word = wq; word < P.Wp; word += Wq) {
+    for (int word = wq; word < P.W; word += Wq) {
       const size_t tb = (size_t)(word / T) * P.n * T;
       const int w = word % T;
       uint64_t f = fr[tb + (size_t)v * T + w] & act[word] & live[word];
@@ -494,11 +494,12 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
         const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T + h0;
         uint64_t vis[H], pl[4][H];
 #pragma unroll
-        for (int w = 0; w < H; w++) vis[w] = valid ? P.vis[base + w] : 0ull;
+        for (int w = 0; w < H; w++) vis[w] = (valid && tile * T + h0 + w < P.W) ? P.vis[base + w] : 0ull;
 #pragma unroll
         for (int b = 0; b < 4; b++)
 #pragma unroll
-          for (int w = 0; w < H; w++) pl[b][w] = (valid && b < P.B) ? P.planes[b * P.pstride + base + w] : 0ull;
+          for (int w = 0; w < H; w++)
+            pl[b][w] = (valid && b < P.B && tile * T + h0 + w < P.W) ? P.planes[b * P.pstride + base + w] : 0ull;
 #pragma unroll
         for (int w = 0; w < H; w++) {
           const int j = tile * T + h0 + w;

@@ -55,7 +55,10 @@ struct HostBuf {
 // ---------------------------------------------------------------- profiling
 enum KernelClass {
   KC_SEED = 0, KC_PUSH, KC_PULL, KC_FINALIZE, KC_SCORE, KC_THRESHOLD, KC_SELECT,
-  KC_FINISH, KC_ANSWER, KC_EXPORT, KC_BUILD, KC_COUNT
+  KC_FINISH, KC_ANSWER, KC_EXPORT, KC_BUILD,
+  // host phases of a batch (wall time): planning and plan upload, kernel
+  // enqueue, waiting for the device, unpacking the results
+  KC_HOST_PLAN, KC_HOST_LAUNCH, KC_HOST_WAIT, KC_HOST_COLLECT, KC_COUNT
 };
 const char *kernel_class_name(int id);
 
@@ -70,6 +73,7 @@ struct Profiler {
   void begin(int cls, hipStream_t s, hipEvent_t *a);
   void end(int cls, hipStream_t s, hipEvent_t a);
   kws_status collect();   // after the stream is synchronised
+  void host(int cls, double ms) { if (on) { launches[cls]++; total_ms[cls] += ms; } }
   void reset();
   void release();
 };

@@ -20,6 +20,7 @@ namespace kws {
 struct Pass {
   // sizes
   int32_t n, T, tiles, Wp, B, nq, n_lanes;
+  int32_t W;                         // words in use; words W..Wp-1 pad the last tile (no lane, no query)
   int32_t chunks, CH, nhist, hist_lds, te_lds;
   int32_t force_dir, count_te;
   float alpha;

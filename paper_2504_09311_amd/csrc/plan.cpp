@@ -278,6 +278,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.T = T;
   P.tiles = tiles;
   P.Wp = tiles * T;
+  P.W = P.Wp;
   P.B = B;
   P.nq = Q.nq;
   P.n_lanes = L.n();

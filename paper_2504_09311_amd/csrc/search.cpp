@@ -5,6 +5,7 @@
 // lanes whose d_max > l and finalizes the arrivals, then scores, ranks and
 // answers every query of the pass.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "engine.h"
@@ -66,6 +67,9 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   const kws_options &o = g->opt;
   const int32_t n = g->n;
   const int nq = qb - qa;
+  using clk = std::chrono::steady_clock;
+  const auto ms_since = [](clk::time_point a) { return std::chrono::duration<double, std::milli>(clk::now() - a).count(); };
+  auto t_phase = clk::now();
   Packing pk;
   pack_queries(qs, qa, qb, o.share_lanes >= 0 && !export_only, pk);
   const int W = (int)pk.word_used.size();
@@ -113,6 +117,7 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
 
   Pass P;
   fill_pass(P, g, E, T, tiles, B, L, lo, Q, qo, al);
+  P.W = W;
   uint64_t *stats = (uint64_t *)(E.arena.as<uint8_t>() + al.extra);
   uint64_t *live = (uint64_t *)(E.zero_region.as<uint8_t>() + al.z_live);
   const uint64_t *act_d = pw.dev<uint64_t>(E, o_act);
@@ -151,15 +156,22 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
     return st;
   }
 
+  g->prof.host(KC_HOST_PLAN, ms_since(t_phase));
+  t_phase = clk::now();
   if (o.use_graph > 0 && !g->prof.on) KWS_TRY(launch_pass_graph(g, P, steps));
   else KWS_TRY(launch_pass(g, P, steps));
   KWS_HIP(hipMemcpyAsync(E.h_arena.p, E.arena.p, al.size, hipMemcpyDeviceToHost, g->stream));
+  g->prof.host(KC_HOST_LAUNCH, ms_since(t_phase));
+  t_phase = clk::now();
   KWS_HIP(hipStreamSynchronize(g->stream));
+  g->prof.host(KC_HOST_WAIT, ms_since(t_phase));
+  t_phase = clk::now();
   KWS_TRY(g->prof.collect());
 
   std::vector<kws_result *> outs(nq);
   for (int i = 0; i < nq; i++) outs[i] = out ? &out[qa + i] : nullptr;
   KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, P.count_te != 0, outs.data(), flat));
+  g->prof.host(KC_HOST_COLLECT, ms_since(t_phase));
 
   const uint64_t *h_stats = (const uint64_t *)(E.h_arena.as<uint8_t>() + al.extra);
   kws_batch_stats &bs = g->last;

@@ -193,6 +193,7 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
 
   Pass P;
   fill_pass(P, g, E, T, tiles, s->B, L, lo, Q, qo, al);
+  P.W = top + 1;
   P.pstride = (size_t)n * s->tiles_alloc * T;   // planes are laid out for every slot
   const int par = (int)(s->step_no & 1);
   uint64_t *live = s->live.as<uint64_t>(), *stats = s->stats.as<uint64_t>();
