@@ -6,7 +6,10 @@ R-MAT(.57,.19,.19,.05) graph with 2^20 vertices and 2^24 sampled edges,
 keywords each, d_max = 3, top-20. One step = one batched pass of the whole
 hot path (plan, seed, level expansion, finalize, root filter and score,
 top-k, answer graphs, result copy) over those 100 queries; inputs (graph,
-labels) are resident in HBM before timing starts.
+labels) are resident in HBM before timing starts. By default the steps are
+pipelined: batch i + 1 is submitted (planned, uploaded, enqueued) before
+batch i is collected, so host planning and result unpacking overlap device
+time; --pipeline 0 times one synchronous call per step instead.
 
 Printed as one JSON line: queries/s of the batched path (value), GTEPS,
 per-step latency percentiles, the plain one-query-per-call path on the same
@@ -196,6 +199,8 @@ def main():
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--graph", type=int, default=0, help="replay a captured hipGraph per batch shape")
+    ap.add_argument("--pipeline", type=int, default=1,
+                    help="1: submit batch i+1 before collecting batch i (host work overlaps the device)")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--plain", type=int, default=100, help="queries timed through the plain path")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
@@ -253,15 +258,30 @@ def main():
     if not args.no_profile:
         G.profile_enable(True)
         G.profile_reset()
-    step_ms = []
+    step_ms, batch_ms = [], []
     te_total = 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for i in range(args.steps):
-        a = time.perf_counter()
-        res = G.search_batch_flat(qs)
-        step_ms.append((time.perf_counter() - a) * 1e3)
-        te_total += te_step
+    if args.pipeline:
+        # batch i + 1 is planned and enqueued while batch i runs on the device
+        t, t_sub = G.search_batch_submit(qs), time.perf_counter()
+        last = t_start
+        for i in range(args.steps):
+            nxt, nxt_sub = (G.search_batch_submit(qs), time.perf_counter()) if i + 1 < args.steps else (None, 0.0)
+            res = G.search_batch_collect(t)
+            now = time.perf_counter()
+            step_ms.append((now - last) * 1e3)
+            batch_ms.append((now - t_sub) * 1e3)
+            last = now
+            t, t_sub = nxt, nxt_sub
+            te_total += te_step
+    else:
+        for i in range(args.steps):
+            a = time.perf_counter()
+            res = G.search_batch_flat(qs)
+            step_ms.append((time.perf_counter() - a) * 1e3)
+            batch_ms.append(step_ms[-1])
+            te_total += te_step
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     G.profile_enable(False)
@@ -345,6 +365,9 @@ def main():
         "gteps": round(gteps, 3),
         "step_latency_ms": dict(p50=round(float(np.percentile(step_ms, 50)), 4),
                                 p99=round(float(np.percentile(step_ms, 99)), 4)),
+        "batch_latency_ms": dict(p50=round(float(np.percentile(batch_ms, 50)), 4),
+                                 p99=round(float(np.percentile(batch_ms, 99)), 4)),
+        "pipelined": bool(args.pipeline),
         "plain": plain,
         "speedup_vs_plain": round(qps / plain["qps"], 2) if plain else None,
         "roofline": roofline,

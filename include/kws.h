@@ -155,6 +155,21 @@ typedef struct {
 kws_status kws_search_batch_flat(kws_graph *g, const kws_query *qs, int32_t nq, kws_batch_result *out);
 void kws_batch_result_free(kws_batch_result *r);
 
+/* Pipelined batches. kws_search_batch_submit plans the batch, uploads its
+ * plan and enqueues its device work and result copy on the handle's stream,
+ * then returns a ticket (> 0) without waiting. kws_search_batch_collect
+ * waits for that batch and fills *out exactly as kws_search_batch_flat
+ * would have (caller frees it with kws_batch_result_free). While one batch
+ * runs on the device the caller can submit the next, so host planning and
+ * result unpacking overlap device time. At most two batches may be
+ * submitted and not collected (KWS_EBUSY beyond); they may be collected in
+ * any order, each once (KWS_EINVAL for an unknown ticket). The queries are
+ * copied at submission. A batch that needs more than one device pass is
+ * computed during submission. kws_last_batch_stats describes the batch
+ * collected last. Batches pending when the graph is freed are dropped. */
+kws_status kws_search_batch_submit(kws_graph *g, const kws_query *qs, int32_t nq, int64_t *ticket);
+kws_status kws_search_batch_collect(kws_graph *g, int64_t ticket, kws_batch_result *out);
+
 /* Verification: dist_n[n] = truncated distance of every vertex to keyword
  * kw (KWS_DIST_INF beyond d_max), computed by the same device kernels. */
 kws_status kws_debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist_n);

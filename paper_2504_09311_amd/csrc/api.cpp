@@ -84,6 +84,8 @@ int64_t dev_bytes_in_use() { return g_dev_bytes.load(); }
 
 kws_status DevBuf::ensure(size_t want, const char *what) {
   if (want <= bytes && p) return KWS_OK;
+  // a pipelined batch may still read the old buffer
+  if (p) (void)hipDeviceSynchronize();
   release();
   size_t b = std::max<size_t>(want, 256);
   p = dev_alloc(b);
@@ -118,12 +120,19 @@ void HostBuf::release() {
   bytes = 0;
 }
 
-void Engine::release() {
-  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags, &plan, &zero_region,
-                 &qsel, &work, &cand, &arena};
+void Engine::IoSet::release() {
+  DevBuf *d[] = {&plan, &zero_region, &qsel, &work, &cand, &arena};
   for (DevBuf *b : d) b->release();
   h_plan.release();
   h_arena.release();
+  if (done) (void)hipEventDestroy(done);
+  done = nullptr;
+}
+
+void Engine::release() {
+  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags};
+  for (DevBuf *b : d) b->release();
+  for (IoSet &x : ios) x.release();
   state_words = 0;
 }
 
@@ -163,16 +172,23 @@ void Profiler::end(int cls, hipStream_t s, hipEvent_t a) {
 }
 
 kws_status Profiler::collect() {
+  // launches of a pipelined batch still on the device stay pending
+  std::vector<Pending> later;
   for (auto &p : pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    const hipError_t e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e == hipErrorNotReady) {
+      later.push_back(p);
+      continue;
+    }
+    if (e == hipSuccess) {
       launches[p.cls]++;
       total_ms[p.cls] += ms;
     }
     pool.push_back(p.a);
     pool.push_back(p.b);
   }
-  pending.clear();
+  pending.swap(later);
   return KWS_OK;
 }
 
@@ -248,16 +264,7 @@ kws_status kws_search_batch(kws_graph *g, const kws_query *qs, int32_t nq, kws_r
   return kws::search(g, qs, nq, out);
 }
 
-kws_status kws_search_batch_flat(kws_graph *g, const kws_query *qs, int32_t nq, kws_batch_result *out) {
-  kws::clear_error();
-  if (!g || !out) return kws::fail(KWS_EINVAL, "null argument");
-  memset(out, 0, sizeof(*out));
-  kws::FlatOut f;
-  {
-    std::lock_guard<std::mutex> lk(g->mu);
-    kws_status st = kws::search(g, qs, nq, nullptr, &f);
-    if (st != KWS_OK) return st;
-  }
+static kws_status flat_to_c(int32_t nq, kws::FlatOut &f, kws_batch_result *out) {
   out->nq = nq;
   out->total_roots = (int64_t)f.roots.size();
   out->root_ptr = copy_out(f.root_ptr);
@@ -277,6 +284,41 @@ kws_status kws_search_batch_flat(kws_graph *g, const kws_query *qs, int32_t nq, 
     return kws::fail(KWS_ENOMEM, "host result allocation");
   }
   return KWS_OK;
+}
+
+kws_status kws_search_batch_flat(kws_graph *g, const kws_query *qs, int32_t nq, kws_batch_result *out) {
+  kws::clear_error();
+  if (!g || !out) return kws::fail(KWS_EINVAL, "null argument");
+  memset(out, 0, sizeof(*out));
+  kws::FlatOut f;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    kws_status st = kws::search(g, qs, nq, nullptr, &f);
+    if (st != KWS_OK) return st;
+  }
+  return flat_to_c(nq, f, out);
+}
+
+kws_status kws_search_batch_submit(kws_graph *g, const kws_query *qs, int32_t nq, int64_t *ticket) {
+  kws::clear_error();
+  if (!g || !ticket) return kws::fail(KWS_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(g->mu);
+  return kws::submit_batch(g, qs, nq, ticket);
+}
+
+kws_status kws_search_batch_collect(kws_graph *g, int64_t ticket, kws_batch_result *out) {
+  kws::clear_error();
+  if (!g || !out) return kws::fail(KWS_EINVAL, "null argument");
+  memset(out, 0, sizeof(*out));
+  kws::FlatOut f;
+  int32_t nq = 0;
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    kws_status st = kws::collect_batch(g, ticket, &f);
+    if (st != KWS_OK) return st;
+    nq = g->last.queries;
+  }
+  return flat_to_c(nq, f, out);
 }
 
 void kws_batch_result_free(kws_batch_result *r) {

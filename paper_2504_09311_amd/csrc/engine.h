@@ -69,7 +69,7 @@ struct PlanWriter {
   size_t add(const void *src, size_t bytes);
   kws_status upload(Engine &E, hipStream_t s);
   template <class T> const T *dev(const Engine &E, size_t off) const {
-    return (const T *)(E.plan.as<uint8_t>() + off);
+    return (const T *)(E.io().plan.as<uint8_t>() + off);
   }
 };
 
@@ -80,6 +80,27 @@ struct ArenaLayout {
   size_t z_live = 0, z_stats = 0, z_ccnt = 0, z_wcnt = 0, z_hist = 0, z_size = 0;
 };
 ArenaLayout arena_layout(const QueryTables &Q, size_t extra_bytes, size_t live_words, size_t stats_words);
+
+// What finishing an enqueued pass needs: its I/O set, query tables, result
+// layout and the shape figures for the batch statistics.
+struct PassRecord {
+  int io = 0;
+  std::vector<const QIn *> qp;
+  QueryTables Q;
+  ArenaLayout al;
+  bool te_counted = false;
+  int nq = 0, lanes = 0, lane_slots = 0, W = 0, Wp = 0, tiles = 0, T = 0, D = 0, direction = 0;
+  float alpha = 0.f;
+};
+
+// A submitted batch: its normalized queries and either an enqueued pass or,
+// when the batch needs several passes, results computed at submission.
+struct AsyncBatch {
+  std::vector<QIn> in;
+  PassRecord rec;
+  bool done = false;
+  FlatOut result;
+};
 
 // Offsets of the query tables inside the plan buffer.
 struct QueryOffsets {

@@ -377,6 +377,7 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
 void free_graph(kws_graph *g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
+  drop_pending(g);
   for (auto &e : g->graphs)
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
   g->graphs.clear();

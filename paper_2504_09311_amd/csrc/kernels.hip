@@ -186,8 +186,8 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
         for (int k = 0; k < TG; k++) {
           const bool ok = v[u] < P.n && t0 + k < P.tiles;
           const size_t idx = ((size_t)(t0 + k) * P.n + v[u]) * T + gl;
-          nxv[u][k] = ok ? P.nxt[idx] : 0ull;
-          oldv[u][k] = ok ? P.vis[idx] : 0ull;
+          nxv[u][k] = ok ? __builtin_nontemporal_load(&P.nxt[idx]) : 0ull;
+          oldv[u][k] = ok ? __builtin_nontemporal_load(&P.vis[idx]) : 0ull;
         }
 #pragma unroll
       for (int k = 0; k < TG; k++) {
@@ -213,11 +213,11 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
               if ((nl >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
           }
           if (S.write_next) {
-            S.fr_next[idx] = fnew;
+            __builtin_nontemporal_store(fnew, &S.fr_next[idx]);
             lacc |= fnew;
             anyneed[u] |= ann & ~nv;
           }
-          if (nx) P.nxt[idx] = 0;
+          if (nx) __builtin_nontemporal_store(0ull, &P.nxt[idx]);
           anyf[u] |= fnew;
         }
         if (t0 == 0) live_acc[k] |= lacc;
@@ -494,12 +494,41 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
         const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T + h0;
         uint64_t vis[H], pl[4][H];
 #pragma unroll
-        for (int w = 0; w < H; w++) vis[w] = (valid && tile * T + h0 + w < P.W) ? P.vis[base + w] : 0ull;
+        for (int w = 0; w < H; w++) vis[w] = 0ull;
 #pragma unroll
         for (int b = 0; b < 4; b++)
 #pragma unroll
+          for (int w = 0; w < H; w++) pl[b][w] = 0ull;
+        if (valid) {
+          // 16-byte loads of the vertex's words (the tile row is 8T-byte aligned)
+          if (H >= 2) {
+#pragma unroll
+            for (int w = 0; w < H; w += 2) {
+              const ulonglong2 x = *(const ulonglong2 *)(P.vis + base + w);
+              vis[w] = x.x; vis[w + 1 < H ? w + 1 : w] = H >= 2 ? x.y : x.x;
+            }
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+              if (b < P.B)
+#pragma unroll
+                for (int w = 0; w < H; w += 2) {
+                  const ulonglong2 x = *(const ulonglong2 *)(P.planes + b * P.pstride + base + w);
+                  pl[b][w] = x.x; pl[b][w + 1 < H ? w + 1 : w] = x.y;
+                }
+          } else {
+            vis[0] = P.vis[base];
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+              if (b < P.B) pl[b][0] = P.planes[b * P.pstride + base];
+          }
+#pragma unroll
           for (int w = 0; w < H; w++)
-            pl[b][w] = (valid && b < P.B && tile * T + h0 + w < P.W) ? P.planes[b * P.pstride + base + w] : 0ull;
+            if (tile * T + h0 + w >= P.W) {   // padding words carry no lane
+              vis[w] = 0ull;
+#pragma unroll
+              for (int b = 0; b < 4; b++) pl[b][w] = 0ull;
+            }
+        }
 #pragma unroll
         for (int w = 0; w < H; w++) {
           const int j = tile * T + h0 + w;

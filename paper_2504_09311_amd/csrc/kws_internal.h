@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -11,6 +12,7 @@
 #include "kws.h"
 
 namespace kws {
+struct AsyncBatch;
 
 // ---------------------------------------------------------------- errors
 kws_status fail(kws_status st, const char *fmt, ...);
@@ -101,14 +103,24 @@ struct Engine {
   size_t state_words = 0;              // words per array currently allocated (n * Wp)
   DevBuf flist, flist_eoff;            // frontier list and in-edge offsets
   DevBuf flags;                        // [2][n] frontier flags (current, next)
-  DevBuf plan;                         // per-pass plan (device copy)
-  DevBuf zero_region;                  // per-pass counters zeroed by the seed kernel
-  DevBuf qsel;                         // per-query top-k threshold
-  DevBuf work;                         // select work items
-  DevBuf cand;                         // top-k candidates
-  DevBuf arena;                        // results (one D2H copy)
-  HostBuf h_plan, h_arena;
-  hipEvent_t done_event = nullptr;
+  // Buffers of one pass in flight. Set 0 serves the synchronous calls; sets
+  // 1 and 2 the two batches a caller may have submitted and not collected.
+  struct IoSet {
+    DevBuf plan;                       // per-pass plan (device copy)
+    DevBuf zero_region;                // per-pass counters zeroed by the seed kernel
+    DevBuf qsel;                       // per-query top-k threshold
+    DevBuf work;                       // select work items
+    DevBuf cand;                       // top-k candidates
+    DevBuf arena;                      // results (one D2H copy)
+    HostBuf h_plan, h_arena;
+    hipEvent_t done = nullptr;         // recorded after the result copy
+    void release();
+  };
+  static constexpr int IO_SETS = 3;
+  IoSet ios[IO_SETS];
+  int cur = 0;                         // the set the pass being planned uses
+  IoSet &io() { return ios[cur]; }
+  const IoSet &io() const { return ios[cur]; }
   void release();
 };
 
@@ -152,6 +164,8 @@ struct kws_graph {
   kws::Profiler prof;
   kws_batch_stats last{};
   std::vector<kws::GraphEntry> graphs;
+  std::map<int64_t, kws::AsyncBatch *> pending;      // submitted, not yet collected batches
+  int64_t next_ticket = 1;
   size_t mem_budget = 0;                             // bytes allowed for search state
 };
 
@@ -167,5 +181,8 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out);
 void free_graph(kws_graph *g);
 void default_options(kws_options *o);
 kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out, FlatOut *flat = nullptr);
+kws_status submit_batch(kws_graph *g, const kws_query *qs, int32_t nq, int64_t *ticket);
+kws_status collect_batch(kws_graph *g, int64_t ticket, FlatOut *flat);
+void drop_pending(kws_graph *g);
 kws_status debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist);
 }  // namespace kws

@@ -200,12 +200,12 @@ size_t PlanWriter::add(const void *src, size_t bytes) {
 }
 
 kws_status PlanWriter::upload(Engine &E, hipStream_t s) {
-  KWS_TRY(E.h_plan.ensure(size, "plan (host)"));
-  KWS_TRY(E.plan.ensure(size, "plan"));
-  uint8_t *hp = E.h_plan.as<uint8_t>();
+  KWS_TRY(E.io().h_plan.ensure(size, "plan (host)"));
+  KWS_TRY(E.io().plan.ensure(size, "plan"));
+  uint8_t *hp = E.io().h_plan.as<uint8_t>();
   for (const Piece &p : pieces)
     if (p.bytes) std::memcpy(hp + p.off, p.src, p.bytes);
-  KWS_HIP(hipMemcpyAsync(E.plan.p, hp, size, hipMemcpyHostToDevice, s));
+  KWS_HIP(hipMemcpyAsync(E.io().plan.p, hp, size, hipMemcpyHostToDevice, s));
   return KWS_OK;
 }
 
@@ -301,7 +301,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.vis = E.vis.as<uint64_t>(); P.fr0 = E.fr0.as<uint64_t>(); P.fr1 = E.fr1.as<uint64_t>();
   P.nxt = E.nxt.as<uint64_t>(); P.planes = E.planes.as<uint64_t>();
   P.flist = E.flist.as<int32_t>(); P.flist_eoff = E.flist_eoff.as<int32_t>();
-  const uint8_t *dp = E.plan.as<uint8_t>();
+  const uint8_t *dp = E.io().plan.as<uint8_t>();
   P.lane_seed_off = (const int64_t *)(dp + lo.seed_off);
   P.lane_seed_begin = (const int32_t *)(dp + lo.seed_begin);
   P.lane_word = (const int32_t *)(dp + lo.word);
@@ -343,8 +343,8 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.word_q_ptr = (const int32_t *)(dp + qo.wq_ptr);
   P.word_q = (const int32_t *)(dp + qo.wq);
   P.bits = dp + qo.bits;
-  uint8_t *ar = E.arena.as<uint8_t>();
-  uint8_t *zr = E.zero_region.as<uint8_t>();
+  uint8_t *ar = E.io().arena.as<uint8_t>();
+  uint8_t *zr = E.io().zero_region.as<uint8_t>();
   P.zero0 = (uint64_t *)ar;
   P.zero0_words = (int64_t)(al.zero_end / 8);
   P.zero1 = (uint64_t *)zr;
@@ -353,9 +353,9 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.cand_cnt = (int32_t *)(zr + al.z_ccnt);
   P.work_cnt = (int32_t *)(zr + al.z_wcnt);
   P.hist = (int32_t *)(zr + al.z_hist);
-  P.qsel = E.qsel.as<int32_t>();
-  P.work = E.work.as<int4>();
-  P.cand = E.cand.as<uint64_t>();
+  P.qsel = E.io().qsel.as<int32_t>();
+  P.work = E.io().work.as<int4>();
+  P.cand = E.io().cand.as<uint64_t>();
   P.r_nroots = (int32_t *)(ar + al.nroots);
   P.r_roots = (int32_t *)(ar + al.roots);
   P.r_scores = (int32_t *)(ar + al.scores);

@@ -61,8 +61,13 @@ kws_status launch_pass_graph(kws_graph *g, const Pass &P, const std::vector<Step
   return KWS_OK;
 }
 
-kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, int max_words, bool export_only,
-                    uint8_t *export_dist, kws_result *out, FlatOut *flat) {
+// Plans a pass over queries [qa, qb) of qs, uploads its plan and enqueues all
+// of its device work and the result copy on the handle's stream, using the
+// engine's current I/O set; finish_pass waits for it and unpacks. With
+// export_dist, the pass (one keyword) copies its distances out instead.
+kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, int max_words,
+                        uint8_t *export_dist, PassRecord &rec) {
+  const bool export_only = export_dist != nullptr;
   Engine &E = g->eng;
   const kws_options &o = g->opt;
   const int32_t n = g->n;
@@ -95,18 +100,20 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
     for (int lv = 0; lv <= li.dmax; lv++) act[(size_t)lv * Wp + li.word] |= 1ull << li.bit;
   std::vector<int8_t> newlvl((size_t)(D + 1) * Wp);
   for (int lv = 0; lv <= D; lv++) std::fill(newlvl.begin() + (size_t)lv * Wp, newlvl.begin() + (size_t)(lv + 1) * Wp, (int8_t)lv);
-  std::vector<const QIn *> qp(nq);
+  std::vector<const QIn *> &qp = rec.qp;
+  qp.resize(nq);
   for (int i = 0; i < nq; i++) qp[i] = &qs[qa + i];
-  QueryTables Q;
+  QueryTables &Q = rec.Q;
   KWS_TRY(Q.build(g, qp, pk.placed, Wp));
 
   const ArenaLayout al = arena_layout(Q, 0, (size_t)(D + 1) * Wp, (size_t)(D + 1) * STAT_WORDS);
-  KWS_TRY(E.arena.ensure(al.size, "result arena"));
-  KWS_TRY(E.h_arena.ensure(al.size, "result arena (host)"));
-  KWS_TRY(E.zero_region.ensure(al.z_size, "counters"));
-  KWS_TRY(E.qsel.ensure(sizeof(int32_t) * 4 * (size_t)nq + 16, "query selection"));
-  KWS_TRY(E.work.ensure(sizeof(int4) * (size_t)std::max<int64_t>(Q.nslots, 1), "select work"));
-  KWS_TRY(E.cand.ensure(8 * (size_t)std::max<int64_t>(Q.ncand, 1), "candidates"));
+  rec.al = al;
+  KWS_TRY(E.io().arena.ensure(al.size, "result arena"));
+  KWS_TRY(E.io().h_arena.ensure(al.size, "result arena (host)"));
+  KWS_TRY(E.io().zero_region.ensure(al.z_size, "counters"));
+  KWS_TRY(E.io().qsel.ensure(sizeof(int32_t) * 4 * (size_t)nq + 16, "query selection"));
+  KWS_TRY(E.io().work.ensure(sizeof(int4) * (size_t)std::max<int64_t>(Q.nslots, 1), "select work"));
+  KWS_TRY(E.io().cand.ensure(8 * (size_t)std::max<int64_t>(Q.ncand, 1), "candidates"));
 
   PlanWriter pw;
   const LaneOffsets lo = add_lane_tables(pw, L);
@@ -118,8 +125,8 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   Pass P;
   fill_pass(P, g, E, T, tiles, B, L, lo, Q, qo, al);
   P.W = W;
-  uint64_t *stats = (uint64_t *)(E.arena.as<uint8_t>() + al.extra);
-  uint64_t *live = (uint64_t *)(E.zero_region.as<uint8_t>() + al.z_live);
+  uint64_t *stats = (uint64_t *)(E.io().arena.as<uint8_t>() + al.extra);
+  uint64_t *live = (uint64_t *)(E.io().zero_region.as<uint8_t>() + al.z_live);
   const uint64_t *act_d = pw.dev<uint64_t>(E, o_act);
   const int8_t *lvl_d = pw.dev<int8_t>(E, o_lvl);
   std::vector<Step> steps;
@@ -160,28 +167,51 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
   t_phase = clk::now();
   if (o.use_graph > 0 && !g->prof.on) KWS_TRY(launch_pass_graph(g, P, steps));
   else KWS_TRY(launch_pass(g, P, steps));
-  KWS_HIP(hipMemcpyAsync(E.h_arena.p, E.arena.p, al.size, hipMemcpyDeviceToHost, g->stream));
+  KWS_HIP(hipMemcpyAsync(E.io().h_arena.p, E.io().arena.p, al.size, hipMemcpyDeviceToHost, g->stream));
+  if (!E.io().done) KWS_HIP(hipEventCreateWithFlags(&E.io().done, hipEventDisableTiming));
+  KWS_HIP(hipEventRecord(E.io().done, g->stream));
   g->prof.host(KC_HOST_LAUNCH, ms_since(t_phase));
-  t_phase = clk::now();
-  KWS_HIP(hipStreamSynchronize(g->stream));
+  rec.io = E.cur;
+  rec.te_counted = P.count_te != 0;
+  rec.nq = nq;
+  rec.lanes = L.n();
+  rec.lane_slots = pk.lane_slots;
+  rec.W = W;
+  rec.Wp = Wp;
+  rec.tiles = tiles;
+  rec.T = T;
+  rec.D = D;
+  rec.direction = o.direction;
+  rec.alpha = o.alpha;
+  return KWS_OK;
+}
+
+// Waits for an enqueued pass, unpacks its results (into out[0..nq) or flat)
+// and adds its statistics to the handle's last-batch statistics.
+kws_status finish_pass(kws_graph *g, PassRecord &rec, kws_result *out, FlatOut *flat) {
+  using clk = std::chrono::steady_clock;
+  const auto ms_since = [](clk::time_point a) { return std::chrono::duration<double, std::milli>(clk::now() - a).count(); };
+  Engine::IoSet &io = g->eng.ios[rec.io];
+  auto t_phase = clk::now();
+  KWS_HIP(hipEventSynchronize(io.done));
   g->prof.host(KC_HOST_WAIT, ms_since(t_phase));
   t_phase = clk::now();
   KWS_TRY(g->prof.collect());
-
+  const int nq = rec.nq, D = rec.D;
   std::vector<kws_result *> outs(nq);
-  for (int i = 0; i < nq; i++) outs[i] = out ? &out[qa + i] : nullptr;
-  KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, P.count_te != 0, outs.data(), flat));
+  for (int i = 0; i < nq; i++) outs[i] = out ? &out[i] : nullptr;
+  KWS_TRY(collect_results(rec.Q, rec.qp, io.h_arena.as<uint8_t>(), rec.al, rec.te_counted, outs.data(), flat));
   g->prof.host(KC_HOST_COLLECT, ms_since(t_phase));
 
-  const uint64_t *h_stats = (const uint64_t *)(E.h_arena.as<uint8_t>() + al.extra);
+  const uint64_t *h_stats = (const uint64_t *)(io.h_arena.as<uint8_t>() + rec.al.extra);
   kws_batch_stats &bs = g->last;
   bs.queries += nq;
-  bs.lanes += L.n();
-  bs.lane_slots += pk.lane_slots;
-  bs.words += W;
-  bs.words_padded += Wp;
-  bs.tiles += tiles;
-  bs.tile_words = T;
+  bs.lanes += rec.lanes;
+  bs.lane_slots += rec.lane_slots;
+  bs.words += rec.W;
+  bs.words_padded += rec.Wp;
+  bs.tiles += rec.tiles;
+  bs.tile_words = rec.T;
   bs.levels = std::max(bs.levels, D);
   bs.passes += 1;
   for (int lv = 0; lv <= D && lv <= KWS_MAX_DMAX; lv++) {
@@ -196,11 +226,20 @@ kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, in
     bs.unfinished_edges[lv] += (int64_t)mu;
     if (lv == D) break;
     int dir = 0;
-    if (nf) dir = (o.direction == 1 || o.direction == 2) ? o.direction
-                  : ((double)o.alpha * mf > (double)mu ? 2 : 1);
+    if (nf) dir = (rec.direction == 1 || rec.direction == 2) ? rec.direction
+                  : ((double)rec.alpha * mf > (double)mu ? 2 : 1);
     bs.pulled[lv] |= dir == 2;
   }
   return KWS_OK;
+}
+
+kws_status run_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb, int max_words, bool export_only,
+                    uint8_t *export_dist, kws_result *out, FlatOut *flat) {
+  PassRecord rec;
+  g->eng.cur = 0;
+  kws_status st = enqueue_pass(g, qs, qa, qb, max_words, export_only ? export_dist : nullptr, rec);
+  if (st != KWS_OK || export_only) return st;
+  return finish_pass(g, rec, out ? out + qa : nullptr, flat);
 }
 
 }  // namespace
@@ -216,6 +255,27 @@ void default_options(kws_options *o) {
   o->count_te = 0;
 }
 
+namespace {
+
+int max_pass_words(const kws_graph *g) {
+  const size_t per_word = (size_t)g->n * 8 * 8;   // vis, 2 frontiers, nxt, 4 planes
+  const size_t budget_words = g->mem_budget / std::max<size_t>(per_word, 1);
+  return (int)std::max<size_t>(1, std::min<size_t>(MAX_WORDS, budget_words));
+}
+
+// Next-fit estimate of the words a batch needs (queries never split).
+int estimate_words(const std::vector<QIn> &in) {
+  int used = 0, free_in_last = 0;
+  for (const QIn &q : in) {
+    if (free_in_last >= q.nk) { free_in_last -= q.nk; continue; }
+    used++;
+    free_in_last = 64 - q.nk;
+  }
+  return used;
+}
+
+}  // namespace
+
 kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out, FlatOut *flat) {
   if (!g || (!qs && nq > 0) || (!out && !flat && nq > 0) || nq < 0) return fail(KWS_EINVAL, "null argument");
   if (out)
@@ -224,9 +284,7 @@ kws_status search(kws_graph *g, const kws_query *qs, int32_t nq, kws_result *out
   for (int i = 0; i < nq; i++) KWS_TRY(normalize_query(g, qs[i], i, in[i]));
   std::memset(&g->last, 0, sizeof(g->last));
   // split into passes that respect the word and memory limits
-  const size_t per_word = (size_t)g->n * 8 * 8;   // vis, 2 frontiers, nxt, 4 planes
-  const size_t budget_words = g->mem_budget / std::max<size_t>(per_word, 1);
-  const int max_words = (int)std::max<size_t>(1, std::min<size_t>(MAX_WORDS, budget_words));
+  const int max_words = max_pass_words(g);
   int qa = 0;
   while (qa < nq) {
     int qb = qa, used_words = 0, free_in_last = 0;
@@ -266,6 +324,66 @@ kws_status debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dis
   kws_status st = run_pass(g, in, 0, 1, 1, true, dist, nullptr, nullptr);
   if (st != KWS_OK) g->eng.state_words = 0;
   return st;
+}
+
+kws_status submit_batch(kws_graph *g, const kws_query *qs, int32_t nq, int64_t *ticket) {
+  if (!g || !ticket || (!qs && nq > 0) || nq < 0) return fail(KWS_EINVAL, "null argument");
+  *ticket = 0;
+  bool held[Engine::IO_SETS] = {};
+  int in_flight = 0;
+  for (auto &kv : g->pending) {
+    in_flight++;
+    if (!kv.second->done) held[kv.second->rec.io] = true;
+  }
+  if (in_flight >= Engine::IO_SETS - 1)
+    return fail(KWS_EBUSY, "%d batches submitted and not collected", in_flight);
+  int io = 1;
+  while (io < Engine::IO_SETS && held[io]) io++;
+  AsyncBatch *b = new AsyncBatch();
+  b->in.resize(nq);
+  for (int i = 0; i < nq; i++) {
+    kws_status st = normalize_query(g, qs[i], i, b->in[i]);
+    if (st != KWS_OK) { delete b; return st; }
+  }
+  const int max_words = max_pass_words(g);
+  kws_status st = PASS_TOO_WIDE;
+  if (nq > 0 && estimate_words(b->in) <= max_words) {
+    g->eng.cur = io;
+    st = enqueue_pass(g, b->in, 0, nq, max_words, nullptr, b->rec);
+    g->eng.cur = 0;
+  }
+  if (st == PASS_TOO_WIDE) {   // several passes (or none): compute now
+    b->done = true;
+    st = search(g, qs, nq, nullptr, &b->result);
+  }
+  if (st != KWS_OK) {
+    g->eng.state_words = 0;   // force a clean reallocation (nxt must start at zero)
+    delete b;
+    return st;
+  }
+  *ticket = g->next_ticket++;
+  g->pending[*ticket] = b;
+  return KWS_OK;
+}
+
+kws_status collect_batch(kws_graph *g, int64_t ticket, FlatOut *flat) {
+  if (!g || !flat) return fail(KWS_EINVAL, "null argument");
+  auto it = g->pending.find(ticket);
+  if (it == g->pending.end()) return fail(KWS_EINVAL, "no submitted batch with ticket %lld", (long long)ticket);
+  AsyncBatch *b = it->second;
+  g->pending.erase(it);
+  kws_status st = KWS_OK;
+  std::memset(&g->last, 0, sizeof(g->last));
+  if (b->done) *flat = std::move(b->result);
+  else st = finish_pass(g, b->rec, nullptr, flat);
+  g->last.queries = (int32_t)b->in.size();
+  delete b;
+  return st;
+}
+
+void drop_pending(kws_graph *g) {
+  for (auto &kv : g->pending) delete kv.second;
+  g->pending.clear();
 }
 
 }  // namespace kws

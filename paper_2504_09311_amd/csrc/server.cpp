@@ -177,12 +177,12 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
   QueryTables Q;
   KWS_TRY(Q.build(g, qp, placed, Wp));
   const ArenaLayout al = arena_layout(Q, 0, 0, 0);
-  KWS_TRY(E.arena.ensure(al.size, "result arena"));
-  KWS_TRY(E.h_arena.ensure(al.size, "result arena (host)"));
-  KWS_TRY(E.zero_region.ensure(al.z_size, "counters"));
-  KWS_TRY(E.qsel.ensure(sizeof(int32_t) * 4 * (size_t)Q.nq + 16, "query selection"));
-  KWS_TRY(E.work.ensure(sizeof(int4) * (size_t)std::max<int64_t>(Q.nslots, 1), "select work"));
-  KWS_TRY(E.cand.ensure(8 * (size_t)std::max<int64_t>(Q.ncand, 1), "candidates"));
+  KWS_TRY(E.io().arena.ensure(al.size, "result arena"));
+  KWS_TRY(E.io().h_arena.ensure(al.size, "result arena (host)"));
+  KWS_TRY(E.io().zero_region.ensure(al.z_size, "counters"));
+  KWS_TRY(E.io().qsel.ensure(sizeof(int32_t) * 4 * (size_t)Q.nq + 16, "query selection"));
+  KWS_TRY(E.io().work.ensure(sizeof(int4) * (size_t)std::max<int64_t>(Q.nslots, 1), "select work"));
+  KWS_TRY(E.io().cand.ensure(8 * (size_t)std::max<int64_t>(Q.ncand, 1), "candidates"));
 
   PlanWriter pw;
   const LaneOffsets lo = add_lane_tables(pw, L);
@@ -223,7 +223,7 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
   KWS_TRY(launch_finalize(P, S, s->stream, s->prof));
   if (Q.nq) {
     KWS_TRY(launch_finish(P, s->stream, s->prof));
-    KWS_HIP(hipMemcpyAsync(E.h_arena.p, E.arena.p, al.size, hipMemcpyDeviceToHost, s->stream));
+    KWS_HIP(hipMemcpyAsync(E.io().h_arena.p, E.io().arena.p, al.size, hipMemcpyDeviceToHost, s->stream));
   }
   KWS_HIP(hipStreamSynchronize(s->stream));
   s->step_no++;
@@ -231,7 +231,7 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
     std::vector<kws_result> res(Q.nq);
     std::vector<kws_result *> outs(Q.nq);
     for (int i = 0; i < Q.nq; i++) outs[i] = &res[i];
-    KWS_TRY(collect_results(Q, qp, E.h_arena.as<uint8_t>(), al, P.count_te != 0, outs.data(), nullptr));
+    KWS_TRY(collect_results(Q, qp, E.io().h_arena.as<uint8_t>(), al, P.count_te != 0, outs.data(), nullptr));
     for (int i = 0; i < Q.nq; i++) done_out.push_back({qtickets[i], res[i]});
   }
   // advance the slots

@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH):
         "kws_result_free": (None, [C.POINTER(ResultC)]),
         "kws_search_batch_flat": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.POINTER(BatchResultC)]),
         "kws_batch_result_free": (None, [C.POINTER(BatchResultC)]),
+        "kws_search_batch_submit": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.POINTER(C.c_int64)]),
+        "kws_search_batch_collect": (C.c_int, [P, C.c_int64, C.POINTER(BatchResultC)]),
         "kws_debug_distances": (C.c_int, [P, C.c_int32, C.c_int32, P]),
         "kws_set_options": (C.c_int, [P, C.POINTER(Options)]),
         "kws_get_options": (C.c_int, [P, C.POINTER(Options)]),
@@ -241,6 +243,7 @@ class Graph:
         h = C.c_void_p()
         _check(lib.kws_load_graph(C.byref(d), C.byref(h)))
         self.h = h
+        self._pending = {}
         self._arrs = None          # the library keeps its own copies
         self.set_options()         # binding default: count te
 
@@ -287,6 +290,23 @@ class Graph:
         n = len(queries)
         r = BatchResultC()
         _check(self._lib.kws_search_batch_flat(self.h, qa, n, C.byref(r)))
+        return self._flat(r, n)
+
+    def search_batch_submit(self, queries) -> int:
+        """kws_search_batch_submit: enqueue a batch and return its ticket without waiting."""
+        qa, keep = _queries(queries)
+        t = C.c_int64()
+        _check(self._lib.kws_search_batch_submit(self.h, qa, len(queries), C.byref(t)))
+        self._pending[int(t.value)] = len(queries)
+        return int(t.value)
+
+    def search_batch_collect(self, ticket: int) -> dict:
+        """kws_search_batch_collect: wait for a submitted batch; same layout as search_batch_flat."""
+        r = BatchResultC()
+        _check(self._lib.kws_search_batch_collect(self.h, int(ticket), C.byref(r)))
+        return self._flat(r, self._pending.pop(int(ticket)))
+
+    def _flat(self, r, n: int) -> dict:
         try:
             nr = int(r.total_roots)
 
@@ -308,11 +328,11 @@ class Graph:
         finally:
             self._lib.kws_batch_result_free(C.byref(r))
 
-    def search_batch(self, queries) -> List[Result]:
-        """Batched search; per-query Result views cut from the flat output."""
-        f = self.search_batch_flat(queries)
+    @staticmethod
+    def results_of(f: dict, n: int) -> List["Result"]:
+        """Per-query Result views cut from a flat batch output."""
         out = []
-        for q in range(len(queries)):
+        for q in range(n):
             a, b = int(f["root_ptr"][q]), int(f["root_ptr"][q + 1])
             kw = f["kw"][f["kw_ptr"][q]:f["kw_ptr"][q + 1]]
             kd = f["kw_dist"][f["dist_ptr"][q]:f["dist_ptr"][q + 1]].reshape(b - a, kw.shape[0])
@@ -321,6 +341,10 @@ class Graph:
             out.append(Result([int(x) for x in kw], f["roots"][a:b], f["scores"][a:b], kd, ep - e0,
                               f["edge_src"][e0:e1], f["edge_dst"][e0:e1], int(f["te"][q])))
         return out
+
+    def search_batch(self, queries) -> List[Result]:
+        """Batched search; per-query Result views cut from the flat output."""
+        return self.results_of(self.search_batch_flat(queries), len(queries))
 
     def debug_distances(self, kw: int, d_max: int) -> np.ndarray:
         n = self.info().n

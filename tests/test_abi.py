@@ -69,6 +69,9 @@ def test_null_arguments():
     assert lib.kws_search_batch(None, None, 0, None) == K.EINVAL
     assert lib.kws_keyword_search(None, None, None) == K.EINVAL
     assert lib.kws_debug_distances(None, 0, 0, None) == K.EINVAL
+    t = C.c_int64()
+    assert lib.kws_search_batch_submit(None, None, 0, C.byref(t)) == K.EINVAL
+    assert lib.kws_search_batch_collect(None, 1, None) == K.EINVAL
     r = B.ResultC()
     lib.kws_result_free(C.byref(r))          # freeing a zeroed result is a no-op
     assert lib.kws_profile_name(0) == b"seed"

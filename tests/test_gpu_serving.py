@@ -4,7 +4,10 @@
   arrived while others were on the device (continuous batching);
 * queries with different radii and keyword counts share slots and steps;
 * cancel, queue-full (EBUSY) and shutdown with work in flight;
-* the hipGraph replay of a batch gives the same answers as direct launches.
+* the hipGraph replay of a batch gives the same answers as direct launches;
+* pipelined batches (submit, then collect) give the same answers as
+  synchronous ones, in any collection order and with synchronous calls
+  interleaved.
 """
 import sys
 import time
@@ -118,6 +121,38 @@ def test_graph_replay_matches(K, rmat14):
         # the program's own eager work between replays
         r = G.keyword_search(qs[rep].kw, qs[rep].d_max, qs[rep].k)
         assert_same(r, want[rep], "eager between replays")
+    G.set_options()
+
+
+def test_pipelined_batches(K, rmat14):
+    g, o, G = rmat14
+    qa = workloads.rmat_flat_queries(64, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=6)
+    qb = workloads.rmat_flat_queries(48, 2, 6, [1, 2, 3], 10, cfg=2, qcfg=7)
+    wa, wb = oracle_results(o, qa), oracle_results(o, qb)
+    for use_graph in (0, 1):
+        G.set_options(use_graph=use_graph)
+        say("pipelined, graph", use_graph)
+        ta = G.search_batch_submit(qa)
+        tb = G.search_batch_submit(qb)
+        with pytest.raises(K.KwsError) as e:          # two in flight at most
+            G.search_batch_submit(qa)
+        assert e.value.status == K.EBUSY
+        # a synchronous call while both are pending
+        assert_same(G.keyword_search(qa[0].kw, qa[0].d_max, qa[0].k), wa[0], "sync between")
+        fb = G.search_batch_collect(tb)            # out of order
+        fa = G.search_batch_collect(ta)
+        assert_all_same(G.results_of(fa, len(qa)), wa, f"pipelined a, graph {use_graph}")
+        assert_all_same(G.results_of(fb, len(qb)), wb, f"pipelined b, graph {use_graph}")
+        with pytest.raises(K.KwsError):
+            G.search_batch_collect(ta)             # each ticket once
+        # a steady pipeline: submit batch i + 1 before collecting batch i
+        order = [(qa, wa), (qb, wb), (qb, wb), (qa, wa), (qa, wa)]
+        t = G.search_batch_submit(order[0][0])
+        for i in range(len(order)):
+            nxt = G.search_batch_submit(order[i + 1][0]) if i + 1 < len(order) else None
+            qs, want = order[i]
+            assert_all_same(G.results_of(G.search_batch_collect(t), len(qs)), want, f"steady {i}")
+            t = nxt
     G.set_options()
 
 
