@@ -790,8 +790,10 @@ __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
         best = block_min(mine, &s_best);
       } else {
         // rows are sorted by neighbour id, so the qualifying neighbours of
-        // the first round that has any include the smallest-id one
-        constexpr int U = 4;
+        // the first round that has any include the smallest-id one; most
+        // walks stop in their first round of BLOCK neighbours, so rounds are
+        // not made longer
+        constexpr int U = 1;
         for (int32_t eb = e0; eb < e1; eb += BLOCK * U) {
           int32_t y[U], mine = 0x7fffffff;
 #pragma unroll
