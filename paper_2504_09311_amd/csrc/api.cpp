@@ -134,6 +134,7 @@ void Engine::release() {
   for (DevBuf *b : d) b->release();
   for (IoSet &x : ios) x.release();
   state_words = 0;
+  state_planes = 0;
 }
 
 // ---------------------------------------------------------------- profiler

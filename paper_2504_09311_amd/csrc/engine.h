@@ -123,7 +123,9 @@ kws_status collect_results(const QueryTables &Q, const std::vector<const QIn *> 
                            const ArenaLayout &al, bool te_counted, kws_result *const *out, FlatOut *flat);
 
 // Per-vertex search state of `words_per_array` words (nxt starts at zero).
-kws_status ensure_state(Engine &E, size_t words_per_array, hipStream_t s);
+// Search state for words_per_array words per array and `planes` distance
+// planes (grows only; nxt is zeroed whenever the arrays are reallocated).
+kws_status ensure_state(Engine &E, size_t words_per_array, int planes, hipStream_t s);
 
 // Tile width for W words: gathered 64-byte lines per edge against streamed words.
 int choose_tile(int W, int max_tile, int64_t n, int64_t m);

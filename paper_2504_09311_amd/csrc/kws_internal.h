@@ -101,6 +101,7 @@ struct Engine {
   // search state, layout [tile][vertex][T words], sized for the largest pass
   DevBuf vis, fr0, fr1, nxt, planes;   // planes: [4][tiles][n][T]
   size_t state_words = 0;              // words per array currently allocated (n * Wp)
+  int state_planes = 0;                // distance planes currently allocated
   DevBuf flist, flist_eoff;            // frontier list and in-edge offsets
   DevBuf flags;                        // [2][n] frontier flags (current, next)
   // Buffers of one pass in flight. Set 0 serves the synchronous calls; sets

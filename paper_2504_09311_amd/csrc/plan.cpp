@@ -430,18 +430,25 @@ kws_status collect_results(const QueryTables &Q, const std::vector<const QIn *> 
   return KWS_OK;
 }
 
-kws_status ensure_state(Engine &E, size_t words_per_array, hipStream_t s) {
-  if (words_per_array <= E.state_words) return KWS_OK;
+kws_status ensure_state(Engine &E, size_t words_per_array, int planes, hipStream_t s) {
+  planes = std::max(planes, 1);
+  if (words_per_array <= E.state_words && planes <= E.state_planes) return KWS_OK;
+  // a pipelined batch may still use the old arrays
+  if (E.vis.p) (void)hipDeviceSynchronize();
+  words_per_array = std::max(words_per_array, E.state_words);
+  planes = std::max(planes, E.state_planes);
   const size_t b = words_per_array * sizeof(uint64_t);
   E.vis.release(); E.fr0.release(); E.fr1.release(); E.nxt.release(); E.planes.release();
   E.state_words = 0;
+  E.state_planes = 0;
   KWS_TRY(E.vis.ensure(b, "vis"));
   KWS_TRY(E.fr0.ensure(b, "frontier"));
   KWS_TRY(E.fr1.ensure(b, "frontier"));
   KWS_TRY(E.nxt.ensure(b, "next"));
-  KWS_TRY(E.planes.ensure(4 * b, "distance planes"));
+  KWS_TRY(E.planes.ensure((size_t)planes * b, "distance planes"));
   KWS_TRY(launch_fill_zero(E.nxt.as<uint64_t>(), words_per_array, s));
   E.state_words = words_per_array;
+  E.state_planes = planes;
   return KWS_OK;
 }
 

@@ -87,7 +87,7 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
   while ((1 << B) <= D) B++;
   if (D == 0) B = 0;
 
-  KWS_TRY(ensure_state(E, (size_t)n * Wp, g->stream));
+  KWS_TRY(ensure_state(E, (size_t)n * Wp, B, g->stream));
   KWS_TRY(E.flist.ensure(sizeof(int32_t) * (size_t)n, "frontier list"));
   KWS_TRY(E.flist_eoff.ensure(sizeof(int32_t) * (size_t)n, "frontier offsets"));
   KWS_TRY(E.flags.ensure(2 * (size_t)n, "frontier flags"));

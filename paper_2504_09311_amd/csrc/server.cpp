@@ -339,6 +339,10 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   // default tile: as wide as the slots allow, up to one 128-byte line of
   // words per vertex (a pull gather moves a whole line)
   if (o.tile_words == 0) o.tile_words = words >= 16 ? 16 : words > 4 ? 8 : words > 2 ? 4 : words > 1 ? 2 : 1;
+  // whole tiles only, within the budget (a tile wider than the slots is the
+  // caller's explicit choice)
+  if (words >= o.tile_words) words = words / o.tile_words * o.tile_words;
+  o.max_words = words;
   kws_server *s = new kws_server();
   s->g = g;
   s->opt = o;
@@ -358,7 +362,7 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
     return bail(kws::fail(KWS_EDEVICE, "stream creation failed"));
   const size_t wp_alloc = (size_t)s->tiles_alloc * s->T;
-  kws_status st = kws::ensure_state(s->eng, (size_t)g->n * wp_alloc, s->stream);
+  kws_status st = kws::ensure_state(s->eng, (size_t)g->n * wp_alloc, B, s->stream);
   if (st == KWS_OK) st = s->eng.flist.ensure(sizeof(int32_t) * (size_t)g->n, "frontier list");
   if (st == KWS_OK) st = s->eng.flist_eoff.ensure(sizeof(int32_t) * (size_t)g->n, "frontier offsets");
   if (st == KWS_OK) st = s->eng.flags.ensure(2 * (size_t)g->n, "frontier flags");
