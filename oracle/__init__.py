@@ -1,12 +1,15 @@
-"""TEST INFRASTRUCTURE: the CPU oracle for distance-bounded keyword search.
+"""TEST INFRASTRUCTURE: the CPU oracles for distance-bounded keyword search
+and for parallel peeling (densest subgraph discovery).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU
 baseline may import this package. The GPU library never does, and the two
 share no code. The arithmetic lives in ``kws_oracle.c`` (plain C, one
-thread, one keyword at a time); this module only marshals arguments.
+thread, one keyword at a time) and ``peel_oracle.c`` (plain C, one thread,
+every round's sums recomputed from scratch); this module only marshals
+arguments.
 
-The definition it implements, and the readings it adopts where the paper
-gives only notation, are stated at the top of ``kws_oracle.c``.
+The definitions they implement, and the readings they adopt where the
+paper is silent, are stated at the top of each C file.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kws_oracle.c")
+_SRC_PEEL = os.path.join(_HERE, "peel_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -28,7 +32,7 @@ def build(force: bool = True, out: str = _LIB, defines=()) -> str:
     """Compile the oracle with gcc into ``out`` (in place by default)."""
     if force or not os.path.exists(out):
         tmp = out + ".tmp"
-        cmd = ["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC]
+        cmd = ["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC, _SRC_PEEL, "-lm"]
         cmd += ["-D" + d for d in defines]
         subprocess.check_call(cmd)
         os.replace(tmp, out)
@@ -51,6 +55,14 @@ def _bind(lib):
     lib.orc_search.argtypes = [C.c_void_p, i32p, C.c_int32, C.c_int32, C.c_int32,
                                C.POINTER(C.c_int32), i32p, C.POINTER(C.c_int32), i32p, i32p,
                                u8p, i64p, i32p, i32p, C.c_int64, C.POINTER(C.c_int64)]
+    lib.orc_fd_weight.restype = C.c_int64
+    lib.orc_fd_weight.argtypes = [C.c_int64]
+    lib.orc_peel.restype = C.c_int
+    lib.orc_peel.argtypes = [C.c_int32, C.c_int64, i32p, i32p, i64p, i64p, C.c_int32, C.c_int32, C.c_int32,
+                             i32p, i64p, i64p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.orc_peel_sequential.restype = C.c_int
+    lib.orc_peel_sequential.argtypes = [C.c_int32, C.c_int64, i32p, i32p, i64p, i64p, u8p,
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     return lib
 
 
@@ -154,3 +166,82 @@ class Oracle:
         return Result([int(x) for x in ukw[:nu]], roots[:nr].copy(), scores[:nr].copy(),
                       kw_dist[: nr * nu].reshape(nr, nu).copy(), edge_ptr[: nr + 1].copy(),
                       es[:ne].copy(), ed[:ne].copy(), int(te.value))
+
+
+# ---------------------------------------------------------------- peeling
+
+PEEL_ALIVE = 0x7FFFFFFF
+METRICS = ("DG", "DW", "FD")
+
+
+def fd_edge_weights(src: np.ndarray, dst: np.ndarray, n: int) -> np.ndarray:
+    """FD edge weights (see peel_oracle.c): 1/ln(deg(src)+5) in 2^-24 units."""
+    lib = load()
+    deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+    table = {}
+    out = np.empty(src.shape[0], np.int64)
+    for e, s in enumerate(src.tolist()):
+        d = int(deg[s])
+        if d not in table:
+            table[d] = int(lib.orc_fd_weight(d))
+        out[e] = table[d]
+    return out
+
+
+def metric_weights(metric: str, src, dst, n: int, edge_w=None, vertex_w=None):
+    """(c, a) for a metric: DG unit edges; DW the given edge weights; FD
+    the log-degree edge weights and the given vertex weights."""
+    m = src.shape[0]
+    if metric == "DG":
+        return np.ones(m, np.int64), np.zeros(n, np.int64)
+    if metric == "DW":
+        return np.ascontiguousarray(edge_w, np.int64), np.zeros(n, np.int64)
+    if metric == "FD":
+        return fd_edge_weights(src, dst, n), np.ascontiguousarray(vertex_w, np.int64)
+    raise ValueError(metric)
+
+
+@dataclass
+class PeelResult:
+    peel_round: np.ndarray    # int32 [n], round in which each vertex is peeled (1-based)
+    sizes: np.ndarray         # int64 [rounds + 1], |S_i|
+    f: np.ndarray             # int64 [rounds + 1], f(S_i)
+    rounds: int
+    best: int                 # index i of the densest S_i
+
+    def best_set(self) -> np.ndarray:
+        return np.flatnonzero(self.peel_round > self.best).astype(np.int32)
+
+
+def peel(n: int, src, dst, c, a, k: int = 2, eps_num: int = 1, eps_den: int = 10, cap: int = 0) -> PeelResult:
+    """Parallel peeling rounds (peel_oracle.c: orc_peel)."""
+    lib = load()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    c = np.ascontiguousarray(c, np.int64)
+    a = np.ascontiguousarray(a, np.int64)
+    cap = cap or n + 2
+    pr = np.empty(max(n, 1), np.int32)
+    sizes = np.empty(cap, np.int64)
+    fs = np.empty(cap, np.int64)
+    r, b = C.c_int32(), C.c_int32()
+    st = lib.orc_peel(n, src.shape[0], src, dst, c, a, k, eps_num, eps_den, pr, sizes, fs, cap,
+                      C.byref(r), C.byref(b))
+    if st != 0:
+        raise ValueError(f"orc_peel failed ({st})")
+    R = int(r.value)
+    return PeelResult(pr[:n].copy(), sizes[:R + 1].copy(), fs[:R + 1].copy(), R, int(b.value))
+
+
+def peel_sequential(n: int, src, dst, c, a):
+    """Sequential peeling (orc_peel_sequential): (set mask, f, size) of the result."""
+    lib = load()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    c = np.ascontiguousarray(c, np.int64)
+    a = np.ascontiguousarray(a, np.int64)
+    mask = np.empty(max(n, 1), np.uint8)
+    bf, bs = C.c_int64(), C.c_int64()
+    if lib.orc_peel_sequential(n, src.shape[0], src, dst, c, a, mask, C.byref(bf), C.byref(bs)) != 0:
+        raise ValueError("orc_peel_sequential failed")
+    return mask[:n].astype(bool), int(bf.value), int(bs.value)

@@ -38,6 +38,9 @@ def _L():
         lib.syn_key.argtypes = [C.c_uint64, C.c_uint64]
         lib.syn_u64.restype = C.c_uint64
         lib.syn_u64.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64]
+        lib.syn_uniform_i64.restype = None
+        lib.syn_uniform_i64.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64,
+                                        np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")]
         lib.syn_permutation.restype = None
         lib.syn_permutation.argtypes = [C.c_int64, C.c_uint64, C.c_uint64, i32p]
         lib.syn_rmat_csr.restype = C.c_int64
@@ -101,6 +104,13 @@ def stream_key(seed: int, stream: int) -> int:
 
 def u64(seed: int, stream: int, ctr: int) -> int:
     return int(_L().syn_u64(seed, stream, ctr))
+
+
+def uniform_i64(seed: int, stream: int, count: int, lo: int, hi: int) -> np.ndarray:
+    """count uniform integers in [lo, hi] from (seed, stream)."""
+    out = np.empty(max(count, 1), np.int64)
+    _L().syn_uniform_i64(seed, stream, count, lo, hi, out)
+    return out[:count]
 
 
 def permutation(n: int, seed: int, stream: int = 15) -> np.ndarray:

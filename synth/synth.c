@@ -54,6 +54,16 @@ uint64_t syn_u64(uint64_t seed, uint64_t stream, uint64_t ctr) {
   return sm_at(sm_key(seed, stream), ctr);
 }
 
+/* out[i] = a uniform integer in [lo, hi] from draw i of (seed, stream),
+ * by multiply-shift of the 64-bit draw (bias below 2^-40 for ranges under
+ * 2^24). */
+void syn_uniform_i64(uint64_t seed, uint64_t stream, int64_t count, int64_t lo, int64_t hi, int64_t *out) {
+  const uint64_t key = sm_key(seed, stream);
+  const unsigned __int128 span = (unsigned __int128)(uint64_t)(hi - lo) + 1u;
+  for (int64_t i = 0; i < count; i++)
+    out[i] = lo + (int64_t)(((unsigned __int128)sm_at(key, (uint64_t)i) * span) >> 64);
+}
+
 /* Fisher-Yates shuffle of 0..n-1, draws from (seed, stream). */
 static void make_perm(int64_t n, uint64_t seed, uint64_t stream, int32_t *perm) {
   uint64_t key = sm_key(seed, stream);

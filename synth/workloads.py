@@ -21,6 +21,15 @@ Recipes (sizes, distributions and seeds):
 
 ``scale`` overrides shrink the R-MAT graphs for fast tests (same recipe,
 fewer vertices; edge factor 16).
+
+Peeling (densest-subgraph) inputs reuse these graphs as directed edge
+lists and add weights from their own seed (graph seed + 0x400): DW edge
+weights uniform on 1..1000 (stream 1), FD vertex weights uniform on
+[0, 2^24) (stream 2, i.e. [0, 1) in 2^-24 units).
+
+* ``peel_chunglu10k``: the chunglu10k graph.
+* ``peel_rmat20``: the rmat20 graph (16,086,343 edges).
+* ``peel_rmat24``: R-MAT 2^24 vertices, 2^28 samples (cfg 4 seeds).
 """
 from __future__ import annotations
 
@@ -106,3 +115,33 @@ def rmat26_serve(scale: int = 26, nq: int = 4096) -> Tuple[Graph, List[Query]]:
 def serve_arrivals(count: int, lam: float):
     _, _, _, sa = _seeds(5)
     return gen.arrivals(count, lam, sa)
+
+
+# ---------------------------------------------------------------- peeling
+
+def peel_input(name: str, scale: Optional[int] = None) -> dict:
+    """A peeling input: n, src, dst (int32 edge list), edge_w (DW), vertex_w (FD)."""
+    import numpy as np
+    if name == "peel_chunglu10k":
+        g, cfg = chunglu10k(), 1
+    elif name == "peel_rmat20":
+        sc = scale or 20
+        cfg = 2
+        gs, _, _, _ = _seeds(cfg)
+        rp, col = gen.rmat_csr(sc, 16 << sc, seed=gs)
+        g = Graph(rp, col, 1, np.zeros(rp.shape[0], np.int32), np.zeros(0, np.int32), None, f"rmat{sc}")
+    elif name == "peel_rmat24":
+        sc = scale or 24
+        cfg = 4
+        gs, _, _, _ = _seeds(cfg)
+        rp, col = gen.rmat_csr(sc, 16 << sc, seed=gs)
+        g = Graph(rp, col, 1, np.zeros(rp.shape[0], np.int32), np.zeros(0, np.int32), None, f"rmat{sc}")
+    else:
+        raise ValueError(name)
+    n = g.n
+    src = np.repeat(np.arange(n, dtype=np.int32), np.diff(g.row_ptr).astype(np.int64))
+    dst = np.ascontiguousarray(g.col, np.int32)
+    ws = SEED_BASE + cfg + 0x400
+    return dict(name=name, n=n, src=src, dst=dst,
+                edge_w=gen.uniform_i64(ws, 1, src.shape[0], 1, 1000),
+                vertex_w=gen.uniform_i64(ws, 2, n, 0, (1 << 24) - 1))
