@@ -1,0 +1,101 @@
+/*
+ * Densest-subgraph discovery by parallel peeling on one AMD Instinct
+ * MI355X (gfx950): C ABI of the peeling part of libkws.so.
+ *
+ * The operation (the paper's Section 2.1, Equation 1, and the parallel
+ * peeling algorithm of Section 4.1, Algorithm 2):
+ *
+ *   G = (V, E), directed edges e = (src, dst) without self-loops; an edge
+ *   is incident to both endpoints. For S a subset of V,
+ *     f(S)   = sum_{u in S} a_u + sum_{e in E, src(e), dst(e) in S} c_e,
+ *     g(S)   = f(S) / |S|,
+ *     w_u(S) = f(S) - f(S \ {u}) (the peeling weight).
+ *   Starting from S_0 = V, round i removes every u in S_{i-1} with
+ *   w_u(S_{i-1}) <= k (1 + eps) g(S_{i-1}), until nothing is left; the
+ *   answer is the first S_i of largest g.
+ *
+ * Metrics (Section 2.1 and the example listing of Section 3):
+ *   KWS_DSD_DG  a = 0, c = 1 (edge density)
+ *   KWS_DSD_DW  a = 0, c = the given edge weight
+ *   KWS_DSD_FD  a = the given vertex weight, c_e = 1 / ln(deg(src(e)) + 5)
+ *               with deg the in- plus out-degree in G, rounded to the
+ *               nearest multiple of 2^-24 (weights are integers in 2^-24
+ *               units, vertex weights included).
+ * All arithmetic is exact integer arithmetic: eps = eps_num / eps_den and
+ * ratios are compared by cross-multiplication, so the rounds, the sizes,
+ * the f values and the answer are deterministic.
+ *
+ * Errors: the kws_status codes of kws.h; kws_last_error() describes the
+ * last failure of the calling thread.
+ */
+#ifndef DSD_H
+#define DSD_H
+
+#include <stdint.h>
+
+#include "kws.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { KWS_DSD_DG = 0, KWS_DSD_DW = 1, KWS_DSD_FD = 2 };
+#define KWS_DSD_ALIVE 0x7fffffff   /* peel round of a vertex never peeled (not returned) */
+
+typedef struct kws_dsd_graph kws_dsd_graph;
+
+/* Host arrays, copied at load (the caller keeps ownership).
+ *   src[m], dst[m]  edge endpoints, 0 <= id < n, src != dst; repeated edges
+ *                   are separate edges
+ *   edge_w[m]       DW edge weights (>= 0, sum below 2^55); NULL for DG and FD
+ *   vertex_w[n]     FD vertex weights (>= 0, 2^-24 units); NULL for DG and DW
+ *   metric          KWS_DSD_DG, KWS_DSD_DW or KWS_DSD_FD
+ * KWS_EINVAL on a malformed graph (nothing is allocated then), KWS_ENOMEM
+ * if the device copies do not fit. */
+typedef struct {
+  int32_t n;
+  int64_t m;
+  const int32_t *src;
+  const int32_t *dst;
+  const int64_t *edge_w;
+  const int64_t *vertex_w;
+  int32_t metric;
+} kws_dsd_desc;
+kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out);
+void kws_dsd_free(kws_dsd_graph *g);
+
+/* k: 2 for the three metrics (the factor of Theorem 4.2); eps_num in
+ * 0..1000, eps_den in 1..1000; profile = 1 times every kernel with HIP
+ * events (the summary's *_ms and launches fields). */
+typedef struct {
+  int32_t k;
+  int32_t eps_num;
+  int32_t eps_den;
+  int32_t profile;
+} kws_dsd_params;
+
+typedef struct {
+  int32_t rounds;        /* R: S_R is empty */
+  int32_t best;          /* index of the densest S_i */
+  int64_t best_size;     /* |S_best| */
+  int64_t best_f;        /* f(S_best) */
+  int64_t incidences;    /* edge endpoints processed by the neighbour updates */
+  double decide_ms, update_ms, reduce_ms;   /* summed kernel time (profile = 1) */
+  int64_t decide_launches, update_launches, reduce_launches;
+} kws_dsd_summary;
+
+/* Runs the peeling on the graph's device copy. Outputs (host memory, each
+ * may be NULL):
+ *   peel_round[n]           the round (1..R) in which each vertex was peeled;
+ *                           S_best = { v : peel_round[v] > best }
+ *   sizes[cap], f[cap]      |S_i| and f(S_i) for i = 0..R
+ * KWS_EOVERFLOW if R + 1 > cap (with sizes or f given), KWS_EINVAL on bad
+ * parameters, KWS_EDEVICE on a device failure. */
+kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel_round, int64_t *sizes,
+                        int64_t *f, int32_t cap, kws_dsd_summary *summary);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,9 +1,10 @@
-"""MI355X (gfx950) distance-bounded graph keyword search.
+"""MI355X (gfx950) distance-bounded graph keyword search, and densest-
+subgraph discovery by parallel peeling.
 
-The hot path lives in the HIP library ``libkws.so`` (C ABI in
-``include/kws.h``); ``kws`` is its ctypes binding.
+The hot paths live in the HIP library ``libkws.so`` (C ABI in
+``include/kws.h`` and ``include/dsd.h``); ``kws`` is its ctypes binding.
 """
 from .kws import (  # noqa: F401
-    Graph, Server, Result, KwsError, load_library, declared_symbols, last_error, set_allocator_torch,
+    Graph, Server, Result, PeelGraph, KwsError, load_library, declared_symbols, last_error, set_allocator_torch,
     OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EBUSY, ECANCELLED, MAX_KW, MAX_DMAX, MAX_K, DIST_INF,
 )

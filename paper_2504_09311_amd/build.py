@@ -1,4 +1,5 @@
-"""Builds ``libkws.so`` (the HIP library behind ``include/kws.h``) in place.
+"""Builds ``libkws.so`` (the HIP library behind ``include/kws.h`` and
+``include/dsd.h``) in place.
 
 Every source is compiled with hipcc for gfx950 only. Packed FP32
 instructions are disabled for all device code.
@@ -15,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkws.so")
-SOURCES = ["graph.hip", "kernels.hip", "plan.cpp", "search.cpp", "server.cpp", "autotune.cpp", "api.cpp"]
+SOURCES = ["graph.hip", "kernels.hip", "plan.cpp", "search.cpp", "server.cpp", "autotune.cpp", "api.cpp", "peel.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1,0 +1,470 @@
+// Densest-subgraph discovery by parallel peeling (the paper's Section 4.1,
+// Algorithm 2), with the DG, DW and FD weight functions of Section 2.1.
+//
+// Layout: every edge is stored twice in an incidence CSR (once in the row
+// of each endpoint) with its weight; per vertex the current peeling weight
+// w (int64), the round it was peeled in, and two ping-pong lists of the
+// vertices still alive. A round is four launches, all on the device:
+//   decide  scan the alive list: w_u * |S| * den <= k * (den + num) * f
+//           (128-bit products) puts u on the peeled list, else on the next
+//           alive list; appends are aggregated per wavefront;
+//   update  one wavefront per peeled vertex subtracts its edge weights from
+//           the neighbours that are still alive (64-bit atomics);
+//   reduce  sum of a + w over the survivors (= 2 f(S_i));
+//   end     one thread: f, |S|, the per-round record and the densest S_i.
+// The host only enqueues rounds and reads |S| every few rounds to stop.
+// Everything is integer arithmetic, so results do not depend on the order
+// of the atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dsd.h"
+#include "kws_internal.h"
+
+namespace kws {
+namespace {
+
+typedef unsigned __int128 u128;
+constexpr int32_t ALIVE = KWS_DSD_ALIVE;
+constexpr int SMALL_DEG = 64;   // rows above this are summed by a wavefront at start
+
+struct PeelScalars {
+  unsigned long long cnt[2];   // lengths of the two alive lists
+  unsigned long long nu;       // vertices peeled in the current round
+  unsigned long long sum2;     // sum of a + w over the survivors
+  unsigned long long inc;      // incidences visited by the updates
+  long long f, s;              // f(S_i), |S_i| of the last finished round
+  long long best_f, best_s;
+  int best_i, pad;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                                                   const int64_t *__restrict__ ew, int64_t m, int metric,
+                                                   const int64_t *__restrict__ fd_table,
+                                                   const int32_t *__restrict__ deg, unsigned long long *fill,
+                                                   int32_t *__restrict__ nbr, int64_t *__restrict__ wt) {
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < m; e += (int64_t)gridDim.x * BLOCK) {
+    const int32_t u = src[e], v = dst[e];
+    int64_t c = 1;
+    if (metric == KWS_DSD_DW) c = ew[e];
+    else if (metric == KWS_DSD_FD) c = fd_table[deg[u]];
+    const unsigned long long p = atomicAdd(&fill[u], 1ull), q = atomicAdd(&fill[v], 1ull);
+    nbr[p] = v;
+    nbr[q] = u;
+    if (wt) { wt[p] = c; wt[q] = c; }
+  }
+}
+
+// initial peeling weights: a_u plus the weights of all incident edges
+__global__ __launch_bounds__(BLOCK) void k_init_small(int32_t n, const int64_t *__restrict__ ptr,
+                                                      const int64_t *__restrict__ wt, const int64_t *__restrict__ a,
+                                                      int64_t *__restrict__ w, int32_t *__restrict__ rnd,
+                                                      int32_t *__restrict__ list) {
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
+    const int64_t b = ptr[v], e = ptr[v + 1];
+    int64_t s = a ? a[v] : 0;
+    if (!wt) s += e - b;
+    else if (e - b <= SMALL_DEG)
+      for (int64_t j = b; j < e; j++) s += wt[j];
+    w[v] = s;   // rows above SMALL_DEG are finished by k_init_big
+    rnd[v] = ALIVE;
+    list[v] = (int32_t)v;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_init_big(const int32_t *__restrict__ big, int32_t nbig,
+                                                    const int64_t *__restrict__ ptr, const int64_t *__restrict__ wt,
+                                                    int64_t *__restrict__ w) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6; i < nbig;
+       i += ((int64_t)gridDim.x * BLOCK) >> 6) {
+    const int32_t v = big[i];
+    unsigned long long s = 0;
+    for (int64_t j = ptr[v] + lane; j < ptr[v + 1]; j += 64) s += (unsigned long long)wt[j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) w[v] += (int64_t)s;
+  }
+}
+
+__global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->cnt[0] = (unsigned long long)n;
+    sc->cnt[1] = 0;
+    sc->nu = sc->sum2 = sc->inc = 0;
+    sc->f = sc->s = sc->best_f = 0;
+    sc->best_i = -1;
+    sc->best_s = 1;
+  }
+}
+
+// wave-aggregated append: returns this lane's slot (valid lanes with flag)
+__device__ __forceinline__ unsigned long long wave_append(bool flag, unsigned long long *counter) {
+  const uint64_t b = __ballot(flag);
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  const int leader = b ? __ffsll((unsigned long long)b) - 1 : 0;
+  if (b && lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(b));
+  base = __shfl(base, leader);
+  return base + (unsigned long long)__popcll(b & ((1ull << lane) - 1ull));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_decide(int32_t round, const int32_t *__restrict__ la, int ca,
+                                                  int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
+                                                  PeelScalars *sc, const int64_t *__restrict__ w,
+                                                  int32_t *__restrict__ rnd, int32_t k, int32_t num, int32_t den) {
+  const unsigned long long count = sc->cnt[ca];
+  const u128 rhs = (u128)(uint64_t)k * (u128)(uint64_t)(den + num) * (u128)(uint64_t)sc->f;
+  const u128 scale = (u128)(uint64_t)sc->s * (u128)(uint64_t)den;
+  // whole wavefronts iterate together so that the appends can use ballots
+  for (unsigned long long base = (unsigned long long)blockIdx.x * BLOCK; base < count;
+       base += (unsigned long long)gridDim.x * BLOCK) {
+    const unsigned long long idx = base + threadIdx.x;
+    const bool valid = idx < count;
+    int32_t v = 0;
+    bool peel = false;
+    if (valid) {
+      v = la[idx];
+      peel = (u128)(uint64_t)w[v] * scale <= rhs;
+    }
+    const unsigned long long pu = wave_append(valid && peel, &sc->nu);
+    const unsigned long long pk = wave_append(valid && !peel, &sc->cnt[cb]);
+    if (valid && peel) {
+      rnd[v] = round;
+      ul[pu] = v;
+    } else if (valid) {
+      lb[pk] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_update(const int32_t *__restrict__ ul, PeelScalars *sc,
+                                                  const int64_t *__restrict__ ptr, const int32_t *__restrict__ nbr,
+                                                  const int64_t *__restrict__ wt, const int32_t *__restrict__ rnd,
+                                                  int64_t *__restrict__ w) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long nu = sc->nu;
+  unsigned long long visited = 0;
+  for (unsigned long long i = ((unsigned long long)blockIdx.x * BLOCK + threadIdx.x) >> 6; i < nu;
+       i += ((unsigned long long)gridDim.x * BLOCK) >> 6) {
+    const int32_t u = ul[i];
+    const int64_t b = ptr[u], e = ptr[u + 1];
+    visited += (unsigned long long)(e - b);
+    for (int64_t j = b + lane; j < e; j += 64) {
+      const int32_t x = nbr[j];
+      if (rnd[x] == ALIVE) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
+    }
+  }
+  if (lane == 0 && visited) atomicAdd(&sc->inc, visited);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ list, int cl, PeelScalars *sc,
+                                                  const int64_t *__restrict__ a, const int64_t *__restrict__ w) {
+  __shared__ unsigned long long s_part[BLOCK / 64];
+  const unsigned long long count = sc->cnt[cl];
+  unsigned long long s = 0;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < count;
+       i += (unsigned long long)gridDim.x * BLOCK) {
+    const int32_t v = list[i];
+    s += (unsigned long long)w[v] + (a ? (unsigned long long)a[v] : 0ull);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int i = 0; i < BLOCK / 64; i++) t += s_part[i];
+    if (t) atomicAdd(&sc->sum2, t);
+  }
+}
+
+// close round `round`: survivors are in list cl; the next round fills 1 - cl
+__global__ void k_end(int32_t round, int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int32_t cap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const long long f = (long long)(sc->sum2 / 2ull), s = (long long)sc->cnt[cl];
+  if (round < cap) { sizes[round] = s; fs[round] = f; }
+  if (s > 0 && (sc->best_i < 0 || (u128)(uint64_t)f * (u128)(uint64_t)sc->best_s >
+                                      (u128)(uint64_t)sc->best_f * (u128)(uint64_t)s)) {
+    sc->best_i = round;
+    sc->best_f = f;
+    sc->best_s = s;
+  }
+  sc->f = f;
+  sc->s = s;
+  sc->sum2 = 0;
+  sc->nu = 0;
+  sc->cnt[1 - cl] = 0;
+}
+
+unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, cap));
+}
+
+}  // namespace
+}  // namespace kws
+
+struct kws_dsd_graph {
+  int32_t n = 0;
+  int64_t m = 0;
+  int metric = 0;
+  int64_t *ptr = nullptr;          // [n + 1] incidence offsets
+  int32_t *nbr = nullptr;          // [2m]
+  int64_t *wt = nullptr;           // [2m] edge weights (none for DG)
+  int64_t *a = nullptr;            // [n] vertex weights (FD only)
+  int32_t *big = nullptr;          // vertices whose row is summed by a wavefront
+  int32_t nbig = 0;
+  int64_t *w = nullptr;            // [n] peeling weights
+  int32_t *rnd = nullptr;          // [n] round of removal
+  int32_t *list[2] = {nullptr, nullptr};
+  int32_t *ul = nullptr;           // [n] peeled in the current round
+  kws::PeelScalars *sc = nullptr;
+  int64_t *d_sizes = nullptr, *d_f = nullptr;
+  int32_t d_cap = 0;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+void dsd_release(kws_dsd_graph *g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  void *ps[] = {g->ptr, g->nbr, g->wt, g->a, g->big, g->w, g->rnd, g->list[0], g->list[1], g->ul, g->sc,
+                g->d_sizes, g->d_f};
+  for (void *p : ps) kws::dev_free(p);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
+template <class T>
+kws_status dev_array(T **p, size_t count, const char *what) {
+  *p = (T *)kws::dev_alloc(sizeof(T) * std::max<size_t>(count, 1));
+  if (!*p) return kws::fail(KWS_ENOMEM, "device allocation for %s (%zu bytes)", what, sizeof(T) * count);
+  return KWS_OK;
+}
+
+// event timing of one kernel class
+struct DsdTimer {
+  bool on;
+  hipStream_t s;
+  double *ms;
+  int64_t *launches;
+  hipEvent_t a = nullptr, b = nullptr;
+  DsdTimer(bool on_, hipStream_t s_, double *ms_, int64_t *l_) : on(on_), s(s_), ms(ms_), launches(l_) {
+    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) hipEventRecord(a, s);
+    else on = false;
+  }
+  ~DsdTimer() {
+    if (!on) return;
+    hipEventRecord(b, s);
+    hipEventSynchronize(b);
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, a, b) == hipSuccess) { *ms += t; (*launches)++; }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
+  using namespace kws;
+  clear_error();
+  if (!d || !out) return fail(KWS_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->n < 0 || d->m < 0 || (d->m > 0 && (!d->src || !d->dst))) return fail(KWS_EINVAL, "bad graph size or arrays");
+  if (d->metric < KWS_DSD_DG || d->metric > KWS_DSD_FD) return fail(KWS_EINVAL, "unknown metric %d", d->metric);
+  if (d->metric == KWS_DSD_DW && d->m > 0 && !d->edge_w) return fail(KWS_EINVAL, "DW needs edge weights");
+  if (d->metric == KWS_DSD_FD && d->n > 0 && !d->vertex_w) return fail(KWS_EINVAL, "FD needs vertex weights");
+  const int32_t n = d->n;
+  const int64_t m = d->m;
+  std::vector<int32_t> deg((size_t)n, 0);
+  u128 tot_e = 0, tot_v = 0;
+  for (int64_t e = 0; e < m; e++) {
+    const int32_t u = d->src[e], v = d->dst[e];
+    if (u < 0 || u >= n || v < 0 || v >= n) return fail(KWS_EINVAL, "edge %lld has an endpoint out of range", (long long)e);
+    if (u == v) return fail(KWS_EINVAL, "edge %lld is a self-loop", (long long)e);
+    if (d->metric == KWS_DSD_DW) {
+      if (d->edge_w[e] < 0) return fail(KWS_EINVAL, "negative edge weight at %lld", (long long)e);
+      tot_e += (u128)(uint64_t)d->edge_w[e];
+    }
+    deg[u]++;
+    deg[v]++;
+  }
+  if (d->metric == KWS_DSD_FD)
+    for (int32_t v = 0; v < n; v++) {
+      if (d->vertex_w[v] < 0) return fail(KWS_EINVAL, "negative vertex weight at %d", v);
+      tot_v += (u128)(uint64_t)d->vertex_w[v];
+    }
+  if (tot_e >= ((u128)1 << 55) || tot_v >= ((u128)1 << 55)) return fail(KWS_EOVERFLOW, "weights sum to 2^55 or more");
+  // FD edge weight by source degree: 1 / ln(deg + 5) in 2^-24 units
+  int32_t maxdeg = 0;
+  for (int32_t v = 0; v < n; v++) maxdeg = std::max(maxdeg, deg[v]);
+  std::vector<int64_t> fd_table;
+  if (d->metric == KWS_DSD_FD) {
+    fd_table.resize((size_t)maxdeg + 1);
+    for (int32_t x = 0; x <= maxdeg; x++) fd_table[x] = std::llround(16777216.0 / std::log((double)x + 5.0));
+  }
+  std::vector<int64_t> ptr((size_t)n + 1, 0);
+  std::vector<int32_t> big;
+  for (int32_t v = 0; v < n; v++) {
+    ptr[v + 1] = ptr[v] + deg[v];
+    if (deg[v] > SMALL_DEG) big.push_back(v);
+  }
+
+  kws_dsd_graph *g = new kws_dsd_graph();
+  g->n = n;
+  g->m = m;
+  g->metric = d->metric;
+  auto bail = [&](kws_status st) { dsd_release(g); return st; };
+  if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(KWS_EDEVICE, "stream creation failed"));
+  hipStream_t s = g->stream;
+  kws_status st = KWS_OK;
+  int32_t *d_src = nullptr, *d_dst = nullptr, *d_deg = nullptr;
+  int64_t *d_ew = nullptr, *d_fd = nullptr;
+  unsigned long long *d_fill = nullptr;
+  auto cleanup = [&]() {
+    dev_free(d_src); dev_free(d_dst); dev_free(d_deg); dev_free(d_ew); dev_free(d_fd); dev_free(d_fill);
+  };
+#define DSD_STEP(x) do { st = (x); if (st != KWS_OK) { cleanup(); return bail(st); } } while (0)
+#define DSD_HIP(x) DSD_STEP((x) == hipSuccess ? KWS_OK : fail(KWS_EDEVICE, "%s failed", #x))
+  DSD_STEP(dev_array(&g->ptr, (size_t)n + 1, "incidence offsets"));
+  DSD_STEP(dev_array(&g->nbr, (size_t)(2 * m), "incidences"));
+  if (d->metric != KWS_DSD_DG) DSD_STEP(dev_array(&g->wt, (size_t)(2 * m), "incidence weights"));
+  if (d->metric == KWS_DSD_FD) DSD_STEP(dev_array(&g->a, (size_t)n, "vertex weights"));
+  DSD_STEP(dev_array(&g->big, big.size(), "large rows"));
+  DSD_STEP(dev_array(&g->w, (size_t)n, "peeling weights"));
+  DSD_STEP(dev_array(&g->rnd, (size_t)n, "peel rounds"));
+  DSD_STEP(dev_array(&g->list[0], (size_t)n, "alive list"));
+  DSD_STEP(dev_array(&g->list[1], (size_t)n, "alive list"));
+  DSD_STEP(dev_array(&g->ul, (size_t)n, "peeled list"));
+  DSD_STEP(dev_array(&g->sc, 1, "peeling scalars"));
+  g->nbig = (int32_t)big.size();
+  DSD_HIP(hipMemcpyAsync(g->ptr, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+  if (!big.empty()) DSD_HIP(hipMemcpyAsync(g->big, big.data(), sizeof(int32_t) * big.size(), hipMemcpyHostToDevice, s));
+  if (g->a) DSD_HIP(hipMemcpyAsync(g->a, d->vertex_w, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  if (m > 0) {
+    DSD_STEP(dev_array(&d_src, (size_t)m, "edge sources"));
+    DSD_STEP(dev_array(&d_dst, (size_t)m, "edge targets"));
+    DSD_STEP(dev_array(&d_fill, (size_t)n + 1, "fill counters"));
+    DSD_HIP(hipMemcpyAsync(d_src, d->src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+    DSD_HIP(hipMemcpyAsync(d_dst, d->dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+    DSD_HIP(hipMemcpyAsync(d_fill, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    if (d->metric == KWS_DSD_DW) {
+      DSD_STEP(dev_array(&d_ew, (size_t)m, "edge weights"));
+      DSD_HIP(hipMemcpyAsync(d_ew, d->edge_w, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, s));
+    }
+    if (d->metric == KWS_DSD_FD) {
+      DSD_STEP(dev_array(&d_fd, fd_table.size(), "FD weight table"));
+      DSD_STEP(dev_array(&d_deg, (size_t)n, "degrees"));
+      DSD_HIP(hipMemcpyAsync(d_fd, fd_table.data(), sizeof(int64_t) * fd_table.size(), hipMemcpyHostToDevice, s));
+      DSD_HIP(hipMemcpyAsync(d_deg, deg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    }
+    k_scatter<<<grid_for(m, BLOCK, 65536), BLOCK, 0, s>>>(d_src, d_dst, d_ew, m, d->metric, d_fd, d_deg, d_fill,
+                                                          g->nbr, g->wt);
+    DSD_HIP(hipGetLastError());
+  }
+  DSD_HIP(hipStreamSynchronize(s));
+  cleanup();
+#undef DSD_HIP
+#undef DSD_STEP
+  *out = g;
+  return KWS_OK;
+}
+
+void kws_dsd_free(kws_dsd_graph *g) { dsd_release(g); }
+
+kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel_round, int64_t *sizes,
+                        int64_t *f, int32_t cap, kws_dsd_summary *summary) {
+  using namespace kws;
+  clear_error();
+  if (!g || !p) return fail(KWS_EINVAL, "null argument");
+  if (p->k < 1 || p->k > 64 || p->eps_num < 0 || p->eps_num > 1000 || p->eps_den < 1 || p->eps_den > 1000)
+    return fail(KWS_EINVAL, "k must be 1..64, eps_num 0..1000, eps_den 1..1000");
+  if ((sizes || f) && cap < 1) return fail(KWS_EINVAL, "cap must be >= 1 with sizes or f");
+  hipStream_t s = g->stream;
+  const int32_t n = g->n;
+  // device record of the rounds: enough for eps > 0 at any size; more is
+  // reallocated when a run needs it
+  const int32_t want_cap = std::max<int32_t>(4096, std::min<int32_t>(n + 2, std::max<int32_t>(cap, 0)));
+  if (g->d_cap < want_cap) {
+    dev_free(g->d_sizes);
+    dev_free(g->d_f);
+    g->d_sizes = g->d_f = nullptr;
+    g->d_cap = 0;
+    KWS_TRY(dev_array(&g->d_sizes, (size_t)want_cap, "round sizes"));
+    KWS_TRY(dev_array(&g->d_f, (size_t)want_cap, "round f"));
+    g->d_cap = want_cap;
+  }
+  kws_dsd_summary sum{};
+  const bool prof = p->profile != 0;
+  const int64_t resident = 2048;
+  KWS_HIP(hipGetLastError());
+  k_scalars_init<<<1, 64, 0, s>>>(g->sc, n);
+  k_init_small<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->ptr, g->wt, g->a, g->w, g->rnd, g->list[0]);
+  if (g->nbig && g->wt) k_init_big<<<grid_for((int64_t)g->nbig * 64, BLOCK, 65536), BLOCK, 0, s>>>(g->big, g->nbig, g->ptr, g->wt, g->w);
+  {
+    DsdTimer t(prof, s, &sum.reduce_ms, &sum.reduce_launches);
+    k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
+  }
+  k_end<<<1, 64, 0, s>>>(0, 0, g->sc, g->d_sizes, g->d_f, g->d_cap);
+  KWS_HIP(hipGetLastError());
+  int64_t known = n;   // an upper bound of |S| (read back every few rounds)
+  int32_t round = 0;
+  while (known > 0) {
+    if (round + 1 >= g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
+    round++;
+    const int ca = (round - 1) & 1, cb = round & 1;
+    {
+      DsdTimer t(prof, s, &sum.decide_ms, &sum.decide_launches);
+      k_decide<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(round, g->list[ca], ca, g->list[cb], cb, g->ul,
+                                                                   g->sc, g->w, g->rnd, p->k, p->eps_num, p->eps_den);
+    }
+    {
+      DsdTimer t(prof, s, &sum.update_ms, &sum.update_launches);
+      k_update<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, g->sc, g->ptr, g->nbr, g->wt, g->rnd,
+                                                                       g->w);
+    }
+    {
+      DsdTimer t(prof, s, &sum.reduce_ms, &sum.reduce_launches);
+      k_reduce<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
+    }
+    k_end<<<1, 64, 0, s>>>(round, cb, g->sc, g->d_sizes, g->d_f, g->d_cap);
+    KWS_HIP(hipGetLastError());
+    if (round % 4 == 0 || known < 4096) {
+      PeelScalars h;
+      KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
+      KWS_HIP(hipStreamSynchronize(s));
+      known = h.s;
+    }
+  }
+  PeelScalars h;
+  KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
+  KWS_HIP(hipStreamSynchronize(s));
+  // R is the first round that left nothing; rounds enqueued past it did nothing
+  std::vector<int64_t> hs((size_t)round + 1), hf((size_t)round + 1);
+  KWS_HIP(hipMemcpyAsync(hs.data(), g->d_sizes, sizeof(int64_t) * hs.size(), hipMemcpyDeviceToHost, s));
+  KWS_HIP(hipMemcpyAsync(hf.data(), g->d_f, sizeof(int64_t) * hf.size(), hipMemcpyDeviceToHost, s));
+  if (peel_round) KWS_HIP(hipMemcpyAsync(peel_round, g->rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+  KWS_HIP(hipStreamSynchronize(s));
+  int32_t R = 0;
+  while (R < round && hs[R] > 0) R++;
+  if ((sizes || f) && R + 1 > cap) return fail(KWS_EOVERFLOW, "%d rounds do not fit cap %d", R, cap);
+  if (sizes) std::memcpy(sizes, hs.data(), sizeof(int64_t) * ((size_t)R + 1));
+  if (f) std::memcpy(f, hf.data(), sizeof(int64_t) * ((size_t)R + 1));
+  sum.rounds = R;
+  sum.best = h.best_i < 0 ? 0 : h.best_i;
+  sum.best_size = h.best_i < 0 ? 0 : h.best_s;
+  sum.best_f = h.best_i < 0 ? 0 : h.best_f;
+  sum.incidences = (int64_t)h.inc;
+  if (summary) *summary = sum;
+  return KWS_OK;
+}
+
+}  // extern "C"

@@ -63,6 +63,22 @@ class Options(C.Structure):
                 ("count_te", C.c_int32), ("seed_mode", C.c_int32)]
 
 
+class DsdDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int64), ("src", C.c_void_p), ("dst", C.c_void_p),
+                ("edge_w", C.c_void_p), ("vertex_w", C.c_void_p), ("metric", C.c_int32)]
+
+
+class DsdParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32), ("profile", C.c_int32)]
+
+
+class DsdSummary(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("best", C.c_int32), ("best_size", C.c_int64), ("best_f", C.c_int64),
+                ("incidences", C.c_int64), ("decide_ms", C.c_double), ("update_ms", C.c_double),
+                ("reduce_ms", C.c_double), ("decide_launches", C.c_int64), ("update_launches", C.c_int64),
+                ("reduce_launches", C.c_int64)]
+
+
 class TuneReport(C.Structure):
     _fields_ = [("configs_tried", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double),
                 ("from_cache", C.c_int32)]
@@ -154,6 +170,9 @@ def load_library(path: str = LIB_PATH):
         "kws_server_cancel": (C.c_int, [P, C.c_uint64]),
         "kws_server_stats_get": (C.c_int, [P, C.POINTER(ServerStats)]),
         "kws_server_destroy": (None, [P]),
+        "kws_dsd_load": (C.c_int, [C.POINTER(DsdDesc), C.POINTER(P)]),
+        "kws_dsd_free": (None, [P]),
+        "kws_dsd_peel": (C.c_int, [P, C.POINTER(DsdParams), P, P, P, C.c_int32, C.POINTER(DsdSummary)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -164,10 +183,10 @@ def load_library(path: str = LIB_PATH):
 
 
 def declared_symbols() -> List[str]:
-    """The function names include/kws.h declares (parsed from the header)."""
+    """The function names the headers in include/ declare (parsed from them)."""
     import re
-    hdr = os.path.join(os.path.dirname(HERE), "include", "kws.h")
-    text = open(hdr).read()
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     return sorted(set(re.findall(r"\b(kws_[a-z_]+)\s*\(", text)))
 
 
@@ -484,3 +503,48 @@ def set_allocator_torch(device: int = 0):
     _torch_hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
     _check(load_library().kws_set_allocator(C.cast(_torch_hooks[0], C.c_void_p),
                                             C.cast(_torch_hooks[1], C.c_void_p), None))
+
+
+class PeelGraph:
+    """Densest-subgraph discovery by parallel peeling (wraps include/dsd.h)."""
+    METRICS = {"DG": 0, "DW": 1, "FD": 2}
+
+    def __init__(self, n: int, src, dst, metric: str, edge_w=None, vertex_w=None):
+        lib = load_library()
+        self._lib = lib
+        self.n = int(n)
+        src = np.ascontiguousarray(src, np.int32)
+        dst = np.ascontiguousarray(dst, np.int32)
+        ew = np.ascontiguousarray(edge_w, np.int64) if edge_w is not None and metric == "DW" else None
+        vw = np.ascontiguousarray(vertex_w, np.int64) if vertex_w is not None and metric == "FD" else None
+        d = DsdDesc(self.n, int(src.shape[0]), src.ctypes.data if src.size else None,
+                    dst.ctypes.data if dst.size else None, ew.ctypes.data if ew is not None else None,
+                    vw.ctypes.data if vw is not None else None, self.METRICS[metric])
+        h = C.c_void_p()
+        _check(lib.kws_dsd_load(C.byref(d), C.byref(h)))
+        self.h = h
+
+    def peel(self, k: int = 2, eps_num: int = 1, eps_den: int = 10, profile: bool = False, cap: int = 0):
+        """(peel_round[n], sizes[R+1], f[R+1], summary dict) of one run."""
+        cap = cap or 65536
+        pr = np.empty(max(self.n, 1), np.int32)
+        sizes = np.empty(cap, np.int64)
+        fs = np.empty(cap, np.int64)
+        sm = DsdSummary()
+        p = DsdParams(k, eps_num, eps_den, 1 if profile else 0)
+        _check(self._lib.kws_dsd_peel(self.h, C.byref(p), pr.ctypes.data, sizes.ctypes.data, fs.ctypes.data, cap,
+                                      C.byref(sm)))
+        R = int(sm.rounds)
+        return pr[:self.n].copy(), sizes[:R + 1].copy(), fs[:R + 1].copy(), \
+            {k2: getattr(sm, k2) for k2, _ in sm._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.kws_dsd_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -108,3 +108,30 @@ def test_server_null_arguments():
     assert lib.kws_server_cancel(None, 1) == K.EINVAL
     lib.kws_server_destroy(None)
     lib.kws_batch_result_free(None)
+
+
+def test_dsd_load_rejects_bad_input():
+    # validation happens on the host before any device call
+    lib = K.load_library()
+    h = C.c_void_p()
+    src = np.array([0, 1, 2], np.int32)
+    dst = np.array([1, 2, 2], np.int32)          # a self-loop
+    ew = np.array([1, 1, 1], np.int64)
+    d = B.DsdDesc(3, 3, src.ctypes.data, dst.ctypes.data, ew.ctypes.data, None, 1)
+    assert lib.kws_dsd_load(C.byref(d), C.byref(h)) == K.EINVAL and not h.value
+    dst2 = np.array([1, 2, 5], np.int32)         # out of range
+    d = B.DsdDesc(3, 3, src.ctypes.data, dst2.ctypes.data, ew.ctypes.data, None, 1)
+    assert lib.kws_dsd_load(C.byref(d), C.byref(h)) == K.EINVAL
+    dst3 = np.array([1, 2, 0], np.int32)
+    d = B.DsdDesc(3, 3, src.ctypes.data, dst3.ctypes.data, None, None, 1)   # DW without weights
+    assert lib.kws_dsd_load(C.byref(d), C.byref(h)) == K.EINVAL
+    d = B.DsdDesc(3, 3, src.ctypes.data, dst3.ctypes.data, None, None, 2)   # FD without vertex weights
+    assert lib.kws_dsd_load(C.byref(d), C.byref(h)) == K.EINVAL
+    neg = np.array([1, -1, 1], np.int64)
+    d = B.DsdDesc(3, 3, src.ctypes.data, dst3.ctypes.data, neg.ctypes.data, None, 1)
+    assert lib.kws_dsd_load(C.byref(d), C.byref(h)) == K.EINVAL
+    d = B.DsdDesc(3, 3, src.ctypes.data, dst3.ctypes.data, None, None, 7)   # unknown metric
+    assert lib.kws_dsd_load(C.byref(d), C.byref(h)) == K.EINVAL
+    assert lib.kws_dsd_load(None, C.byref(h)) == K.EINVAL
+    assert lib.kws_dsd_peel(None, None, None, None, None, 0, None) == K.EINVAL
+    assert K.last_error()
