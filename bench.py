@@ -94,7 +94,7 @@ def byte_model(st: dict, n: int, kernel: str) -> float:
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when there is none or
-    the kernel source changed since the counters were taken."""
+    the kernel's source file changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
@@ -105,9 +105,11 @@ def measured_traffic(kernel: str, workload: str):
         if ":" in line:
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2504_09311_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2504_09311_amd", "csrc", fields.get("source", "kernels.hip"))
+    if not os.path.exists(src):
+        return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernels_hip_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
         return None
     return int(float(fields["traffic_bytes_per_launch"]))
 
@@ -187,6 +189,90 @@ def serve_bench(G, K, g, qs, args):
                 poisson=runs)
 
 
+PEEL_METRIC = "densest-subgraph parallel peeling (eps=0.1): edges per second over a full run; rounds; time"
+
+
+def peel_bytes(metric: str, n: int, sizes, summary) -> dict:
+    """Algorithmic bytes of one run per kernel class: decide reads the alive
+    list and w and writes one list entry (plus the peel round of a peeled
+    vertex): 20 B per alive vertex; update reads the neighbour id, its peel
+    round and the edge weight (not for DG) and adds to w: 24 (DG) or 32 B
+    per incidence; reduce reads list entry, w and a (FD): 12 or 20 B per
+    survivor."""
+    alive_before = int(sum(sizes[:-1]))
+    survivors = int(sum(sizes[1:])) + int(sizes[0])
+    inc = int(summary["incidences"])
+    return dict(decide=20.0 * alive_before,
+                update=(24.0 if metric == "DG" else 32.0) * inc,
+                reduce=(20.0 if metric == "FD" else 12.0) * survivors)
+
+
+def peel_bench(args):
+    """Parallel peeling on a peeling input: every metric timed over full runs."""
+    import torch
+    import paper_2504_09311_amd as K
+    from synth import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    inp = W.peel_input(args.workload, scale=args.scale)
+    n, src, dst = inp["n"], inp["src"], inp["dst"]
+    m = int(src.shape[0])
+    log("peeling input", args.workload, n, "vertices", m, "edges")
+    per = {}
+    roof = None
+    for metric in ("DG", "DW", "FD"):
+        t0 = time.perf_counter()
+        G = K.PeelGraph(n, src, dst, metric, edge_w=inp["edge_w"], vertex_w=inp["vertex_w"])
+        load_s = time.perf_counter() - t0
+        for _ in range(max(1, args.warmup)):
+            G.peel(2, 1, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pr, sizes, fs, sm = G.peel(2, 1, 10)
+        wall = (time.perf_counter() - t0) / args.steps
+        # one profiled run for the per-kernel times (events serialise it)
+        _, sizes_p, _, smp = G.peel(2, 1, 10, profile=True)
+        G.close()
+        bytes_ = peel_bytes(metric, n, sizes_p, smp)
+        kern = {k: dict(launches=int(smp[k + "_launches"]), total_ms=round(smp[k + "_ms"], 4),
+                        avg_us=round(smp[k + "_ms"] * 1e3 / max(1, smp[k + "_launches"]), 3)) for k in bytes_}
+        per[metric] = dict(seconds=round(wall, 5), edges_per_s=round(m / wall, 1), rounds=int(sm["rounds"]),
+                           best=int(sm["best"]), best_size=int(sm["best_size"]), best_f=int(sm["best_f"]),
+                           load_s=round(load_s, 3), kernels=kern)
+        if metric == "DG":
+            dom = max(kern, key=lambda k: kern[k]["total_ms"])
+            launches = kern[dom]["launches"]
+            per_launch = bytes_[dom] / launches
+            avg_s = kern[dom]["total_ms"] / 1e3 / launches
+            roof = dict(kernel=dom, bound="hbm", achieved=round(per_launch / avg_s / 1e9, 2), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                        traffic=measured_traffic("peel_" + dom, args.workload),
+                        bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 3), launches=launches)
+        log(metric, per[metric])
+    cpu = None
+    if args.cpu_budget > 0:
+        import oracle
+        # the oracle recomputes every sum in every round; a bounded sample is
+        # the same recipe at 2^20 vertices when the input is larger
+        sample = inp if m <= (1 << 25) else W.peel_input("peel_rmat20")
+        c, a = oracle.metric_weights("DG", sample["src"], sample["dst"], sample["n"])
+        t0 = time.perf_counter()
+        oracle.peel(sample["n"], sample["src"], sample["dst"], c, a, 2, 1, 10, cap=4096)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=round(sample["src"].shape[0] / dt, 1), unit="edges/s", cores=1, kind="oracle",
+                   sample=f"DG peeling of {sample['name']} ({sample['n']} vertices, {sample['src'].shape[0]} "
+                          f"edges), one full run in {dt:.1f} s")
+    out = {
+        "metric": PEEL_METRIC, "value": per["DG"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per["DG"]["seconds"] * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": dict(workload=args.workload, n=n, m=m, eps="1/10", k=2, metric="DG (DW, FD alongside)"),
+        "per_metric": per, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +296,13 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each Poisson run")
     ap.add_argument("--serve-words", type=int, default=0, help="server word slots (0 = memory budget)")
     args = ap.parse_args()
+
+    if args.workload.startswith("peel_"):
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        peel_bench(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

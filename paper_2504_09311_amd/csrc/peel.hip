@@ -8,8 +8,10 @@
 //   decide  scan the alive list: w_u * |S| * den <= k * (den + num) * f
 //           (128-bit products) puts u on the peeled list, else on the next
 //           alive list; appends are aggregated per wavefront;
-//   update  one wavefront per peeled vertex subtracts its edge weights from
-//           the neighbours that are still alive (64-bit atomics);
+//   update  push: the peeled vertices subtract their edge weights from the
+//           neighbours still alive (64-bit atomics); or pull: the survivors
+//           re-sum their alive neighbours (rows split over blocks), whichever
+//           set has fewer incidences (chosen on the device);
 //   reduce  sum of a + w over the survivors (= 2 f(S_i));
 //   end     one thread: f, |S|, the per-round record and the densest S_i.
 // The host only enqueues rounds and reads |S| every few rounds to stop.
@@ -32,12 +34,15 @@ namespace {
 typedef unsigned __int128 u128;
 constexpr int32_t ALIVE = KWS_DSD_ALIVE;
 constexpr int SMALL_DEG = 64;   // rows above this are summed by a wavefront at start
+constexpr int SMALL_PUSH = 16;  // peeled rows up to this are pushed by one thread
 
 struct PeelScalars {
   unsigned long long cnt[2];   // lengths of the two alive lists
-  unsigned long long nu;       // vertices peeled in the current round
+  unsigned long long nu;       // vertices peeled in the current round with small rows
+  unsigned long long nu_big;   // ... with rows above SMALL_PUSH incidences (listed from the end)
   unsigned long long sum2;     // sum of a + w over the survivors
-  unsigned long long inc;      // incidences visited by the updates
+  unsigned long long deg_peel; // incidences of the vertices peeled in the current round
+  unsigned long long deg_keep; // incidences of the survivors
   long long f, s;              // f(S_i), |S_i| of the last finished round
   long long best_f, best_s;
   int best_i, pad;
@@ -95,71 +100,180 @@ __global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->cnt[0] = (unsigned long long)n;
     sc->cnt[1] = 0;
-    sc->nu = sc->sum2 = sc->inc = 0;
+    sc->nu = sc->nu_big = sc->sum2 = sc->deg_peel = sc->deg_keep = 0;
     sc->f = sc->s = sc->best_f = 0;
     sc->best_i = -1;
     sc->best_s = 1;
   }
 }
 
-// wave-aggregated append: returns this lane's slot (valid lanes with flag)
-__device__ __forceinline__ unsigned long long wave_append(bool flag, unsigned long long *counter) {
-  const uint64_t b = __ballot(flag);
-  const int lane = threadIdx.x & 63;
-  unsigned long long base = 0;
-  const int leader = b ? __ffsll((unsigned long long)b) - 1 : 0;
-  if (b && lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(b));
-  base = __shfl(base, leader);
-  return base + (unsigned long long)__popcll(b & ((1ull << lane) - 1ull));
+// exclusive prefix sum over the block of one value per thread
+__device__ __forceinline__ unsigned block_excl_scan(unsigned x, unsigned *s_w, unsigned *total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned v = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned y = __shfl_up(v, off);
+    if (lane >= off) v += y;
+  }
+  if (lane == 63) s_w[wid] = v;
+  __syncthreads();
+  unsigned before = 0, all = 0;
+  for (int i = 0; i < BLOCK / 64; i++) {
+    if (i < wid) before += s_w[i];
+    all += s_w[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + v - x;
 }
+
+// decide: a block takes CHUNK alive vertices at a time (PER per thread,
+// strided so loads coalesce), tests each, and appends the peeled and the
+// surviving ones with one reservation per list and chunk; the degree sums
+// of both sets choose how the weights are updated
+constexpr int PER = 16, CHUNK = PER * BLOCK;
 
 __global__ __launch_bounds__(BLOCK) void k_decide(int32_t round, const int32_t *__restrict__ la, int ca,
                                                   int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
-                                                  PeelScalars *sc, const int64_t *__restrict__ w,
-                                                  int32_t *__restrict__ rnd, int32_t k, int32_t num, int32_t den) {
+                                                  int32_t n_total, PeelScalars *sc, const int64_t *__restrict__ w,
+                                                  const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd,
+                                                  int32_t k, int32_t num, int32_t den) {
+  __shared__ unsigned s_w[BLOCK / 64];
+  __shared__ unsigned long long s_base[3];
   const unsigned long long count = sc->cnt[ca];
   const u128 rhs = (u128)(uint64_t)k * (u128)(uint64_t)(den + num) * (u128)(uint64_t)sc->f;
   const u128 scale = (u128)(uint64_t)sc->s * (u128)(uint64_t)den;
-  // whole wavefronts iterate together so that the appends can use ballots
-  for (unsigned long long base = (unsigned long long)blockIdx.x * BLOCK; base < count;
-       base += (unsigned long long)gridDim.x * BLOCK) {
-    const unsigned long long idx = base + threadIdx.x;
-    const bool valid = idx < count;
-    int32_t v = 0;
-    bool peel = false;
-    if (valid) {
-      v = la[idx];
-      peel = (u128)(uint64_t)w[v] * scale <= rhs;
+  for (unsigned long long c0 = (unsigned long long)blockIdx.x * CHUNK; c0 < count;
+       c0 += (unsigned long long)gridDim.x * CHUNK) {
+    int32_t v[PER];
+    unsigned peel_bits = 0, big_bits = 0, np = 0, nb = 0, nk = 0;
+    unsigned long long dp = 0, dk = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      const unsigned long long idx = c0 + (unsigned long long)j * BLOCK + threadIdx.x;
+      v[j] = idx < count ? la[idx] : -1;
     }
-    const unsigned long long pu = wave_append(valid && peel, &sc->nu);
-    const unsigned long long pk = wave_append(valid && !peel, &sc->cnt[cb]);
-    if (valid && peel) {
-      rnd[v] = round;
-      ul[pu] = v;
-    } else if (valid) {
-      lb[pk] = v;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      if (v[j] < 0) continue;
+      const unsigned long long d = (unsigned long long)(ptr[v[j] + 1] - ptr[v[j]]);
+      if ((u128)(uint64_t)w[v[j]] * scale <= rhs) {
+        peel_bits |= 1u << j;
+        if (d > SMALL_PUSH) { big_bits |= 1u << j; nb++; } else np++;
+        dp += d;
+      } else {
+        nk++;
+        dk += d;
+      }
+    }
+    unsigned tp, tb, tk;
+    const unsigned op = block_excl_scan(np, s_w, &tp);
+    const unsigned ob = block_excl_scan(nb, s_w, &tb);
+    const unsigned ok = block_excl_scan(nk, s_w, &tk);
+    for (int off = 32; off > 0; off >>= 1) {
+      dp += __shfl_xor(dp, off);
+      dk += __shfl_xor(dk, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (dp) atomicAdd(&sc->deg_peel, dp);
+      if (dk) atomicAdd(&sc->deg_keep, dk);
+    }
+    if (threadIdx.x == 0) {
+      s_base[0] = tp ? atomicAdd(&sc->nu, (unsigned long long)tp) : 0ull;
+      s_base[1] = tk ? atomicAdd(&sc->cnt[cb], (unsigned long long)tk) : 0ull;
+      s_base[2] = tb ? atomicAdd(&sc->nu_big, (unsigned long long)tb) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long pu = s_base[0] + op, pk = s_base[1] + ok, pb = s_base[2] + ob;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      if (v[j] < 0) continue;
+      if ((peel_bits >> j) & 1u) {
+        rnd[v[j]] = round;
+        if ((big_bits >> j) & 1u) ul[n_total - 1 - pb++] = v[j];   // large rows fill the list from its end
+        else ul[pu++] = v[j];
+      } else {
+        lb[pk++] = v[j];
+      }
     }
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_update(const int32_t *__restrict__ ul, PeelScalars *sc,
-                                                  const int64_t *__restrict__ ptr, const int32_t *__restrict__ nbr,
-                                                  const int64_t *__restrict__ wt, const int32_t *__restrict__ rnd,
-                                                  int64_t *__restrict__ w) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long nu = sc->nu;
-  unsigned long long visited = 0;
-  for (unsigned long long i = ((unsigned long long)blockIdx.x * BLOCK + threadIdx.x) >> 6; i < nu;
-       i += ((unsigned long long)gridDim.x * BLOCK) >> 6) {
+// push: the peeled vertices subtract their edge weights from the neighbours
+// still alive; a thread per vertex with a small row, a wavefront per vertex
+// with a large one. Runs when the peeled vertices have no more incidences
+// than the survivors.
+__global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict__ ul, int32_t n_total,
+                                                       PeelScalars *sc, const int64_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ nbr,
+                                                       const int64_t *__restrict__ wt,
+                                                       const int32_t *__restrict__ rnd, int64_t *__restrict__ w) {
+  if (sc->deg_peel > sc->deg_keep) return;
+  const unsigned long long nu = sc->nu, nb = sc->nu_big;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < nu;
+       i += (unsigned long long)gridDim.x * BLOCK) {
     const int32_t u = ul[i];
+    for (int64_t j = ptr[u]; j < ptr[u + 1]; j++) {
+      const int32_t x = nbr[j];
+      if (rnd[x] == ALIVE) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  for (unsigned long long i = ((unsigned long long)blockIdx.x * BLOCK + threadIdx.x) >> 6; i < nb;
+       i += ((unsigned long long)gridDim.x * BLOCK) >> 6) {
+    const int32_t u = ul[n_total - 1 - i];
     const int64_t b = ptr[u], e = ptr[u + 1];
-    visited += (unsigned long long)(e - b);
     for (int64_t j = b + lane; j < e; j += 64) {
       const int32_t x = nbr[j];
       if (rnd[x] == ALIVE) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
     }
   }
-  if (lane == 0 && visited) atomicAdd(&sc->inc, visited);
+}
+
+// pull (when the survivors have fewer incidences than the peeled vertices):
+// the survivors' weights restart from a and every block adds the alive
+// neighbours of its part of one survivor's row; the blocks share the
+// survivors, several blocks per row when there are fewer survivors than
+// blocks, so a handful of high-degree survivors still fill the chip.
+__global__ __launch_bounds__(BLOCK) void k_update_pull_reset(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+                                                             const int64_t *__restrict__ a, int64_t *__restrict__ w) {
+  if (sc->deg_peel <= sc->deg_keep) return;
+  const unsigned long long count = sc->cnt[cb];
+  for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < count;
+       i += (unsigned long long)gridDim.x * BLOCK)
+    w[lb[i]] = a ? a[lb[i]] : 0;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_update_pull(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+                                                       const int64_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ nbr,
+                                                       const int64_t *__restrict__ wt,
+                                                       const int32_t *__restrict__ rnd, int64_t *__restrict__ w) {
+  __shared__ unsigned long long s_part[BLOCK / 64];
+  if (sc->deg_peel <= sc->deg_keep) return;
+  const unsigned long long count = sc->cnt[cb];
+  if (count == 0) return;
+  const unsigned long long bps = max(1ull, (unsigned long long)gridDim.x / count);   // blocks per row
+  for (unsigned long long it = blockIdx.x; it < count * bps; it += gridDim.x) {
+    const int32_t v = lb[it / bps];
+    const unsigned long long part = it % bps;
+    const int64_t b = ptr[v], len = ptr[v + 1] - b;
+    const int64_t lo = b + (int64_t)((unsigned long long)len * part / bps);
+    const int64_t hi = b + (int64_t)((unsigned long long)len * (part + 1) / bps);
+    unsigned long long s = 0;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += BLOCK)
+      if (rnd[nbr[j]] == ALIVE) s += (unsigned long long)(wt ? wt[j] : 1ll);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int i = 0; i < BLOCK / 64; i++) t += s_part[i];
+      if (t) atomicAdd((unsigned long long *)&w[v], t);
+    }
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ list, int cl, PeelScalars *sc,
@@ -196,7 +310,8 @@ __global__ void k_end(int32_t round, int cl, PeelScalars *sc, int64_t *sizes, in
   sc->f = f;
   sc->s = s;
   sc->sum2 = 0;
-  sc->nu = 0;
+  sc->nu = sc->nu_big = 0;
+  sc->deg_peel = sc->deg_keep = 0;
   sc->cnt[1 - cl] = 0;
 }
 
@@ -423,13 +538,17 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     const int ca = (round - 1) & 1, cb = round & 1;
     {
       DsdTimer t(prof, s, &sum.decide_ms, &sum.decide_launches);
-      k_decide<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(round, g->list[ca], ca, g->list[cb], cb, g->ul,
-                                                                   g->sc, g->w, g->rnd, p->k, p->eps_num, p->eps_den);
+      k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(round, g->list[ca], ca, g->list[cb], cb, g->ul,
+                                                                   n, g->sc, g->w, g->ptr, g->rnd, p->k, p->eps_num,
+                                                                   p->eps_den);
     }
     {
       DsdTimer t(prof, s, &sum.update_ms, &sum.update_launches);
-      k_update<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, g->sc, g->ptr, g->nbr, g->wt, g->rnd,
-                                                                       g->w);
+      k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, g->ptr, g->nbr, g->wt,
+                                                                            g->rnd, g->w);
+      k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
+      k_update_pull<<<(unsigned)resident, BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->ptr, g->nbr, g->wt, g->rnd,
+                                                         g->w);
     }
     {
       DsdTimer t(prof, s, &sum.reduce_ms, &sum.reduce_launches);
@@ -462,7 +581,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   sum.best = h.best_i < 0 ? 0 : h.best_i;
   sum.best_size = h.best_i < 0 ? 0 : h.best_s;
   sum.best_f = h.best_i < 0 ? 0 : h.best_f;
-  sum.incidences = (int64_t)h.inc;
+  sum.incidences = 2 * g->m;   // every vertex is peeled once: each edge is visited from both ends
   if (summary) *summary = sum;
   return KWS_OK;
 }
