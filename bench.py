@@ -207,6 +207,17 @@ def peel_bytes(metric: str, n: int, sizes, summary) -> dict:
                 reduce=(20.0 if metric == "FD" else 12.0) * survivors)
 
 
+def copy_probe(mb: int):
+    """Three plain device copies of `mb` MiB: the reference dispatch that
+    scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    x = torch.empty(mb << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+
+
 def peel_bench(args):
     """Parallel peeling on a peeling input: every metric timed over full runs."""
     import torch
@@ -220,27 +231,36 @@ def peel_bench(args):
     log("peeling input", args.workload, n, "vertices", m, "edges")
     per = {}
     roof = None
-    for metric in ("DG", "DW", "FD"):
+    metrics = [x for x in args.peel_metrics.split(",") if x]
+    assert metrics and set(metrics) <= {"DG", "DW", "FD"}, args.peel_metrics
+    for metric in metrics:
         t0 = time.perf_counter()
         G = K.PeelGraph(n, src, dst, metric, edge_w=inp["edge_w"], vertex_w=inp["vertex_w"])
         load_s = time.perf_counter() - t0
+        # the peel rounds stay in HBM in the timed runs (inputs and outputs
+        # resident); one more run returns them to host memory
         for _ in range(max(1, args.warmup)):
-            G.peel(2, 1, 10)
+            G.peel(2, 1, 10, rounds=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            pr, sizes, fs, sm = G.peel(2, 1, 10)
+            _, sizes, fs, sm = G.peel(2, 1, 10, rounds=False)
+        torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        G.peel(2, 1, 10)
+        wall_host = time.perf_counter() - t0
         # one profiled run for the per-kernel times (events serialise it)
-        _, sizes_p, _, smp = G.peel(2, 1, 10, profile=True)
+        _, sizes_p, _, smp = G.peel(2, 1, 10, profile=True, rounds=False)
         G.close()
         bytes_ = peel_bytes(metric, n, sizes_p, smp)
         kern = {k: dict(launches=int(smp[k + "_launches"]), total_ms=round(smp[k + "_ms"], 4),
                         avg_us=round(smp[k + "_ms"] * 1e3 / max(1, smp[k + "_launches"]), 3)) for k in bytes_}
-        per[metric] = dict(seconds=round(wall, 5), edges_per_s=round(m / wall, 1), rounds=int(sm["rounds"]),
+        per[metric] = dict(seconds=round(wall, 5), edges_per_s=round(m / wall, 1),
+                           seconds_host_output=round(wall_host, 5), rounds=int(sm["rounds"]),
                            best=int(sm["best"]), best_size=int(sm["best_size"]), best_f=int(sm["best_f"]),
                            load_s=round(load_s, 3), kernels=kern)
-        if metric == "DG":
+        if metric == metrics[0]:
             dom = max(kern, key=lambda k: kern[k]["total_ms"])
             launches = kern[dom]["launches"]
             per_launch = bytes_[dom] / launches
@@ -250,8 +270,10 @@ def peel_bench(args):
                         traffic=measured_traffic("peel_" + dom, args.workload),
                         bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 3), launches=launches)
         log(metric, per[metric])
+    if args.copy_probe_mb:
+        copy_probe(args.copy_probe_mb)
     cpu = None
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and metrics[0] == "DG":
         import oracle
         # the oracle recomputes every sum in every round; a bounded sample is
         # the same recipe at 2^20 vertices when the input is larger
@@ -263,11 +285,13 @@ def peel_bench(args):
         cpu = dict(value=round(sample["src"].shape[0] / dt, 1), unit="edges/s", cores=1, kind="oracle",
                    sample=f"DG peeling of {sample['name']} ({sample['n']} vertices, {sample['src'].shape[0]} "
                           f"edges), one full run in {dt:.1f} s")
+    lead = metrics[0]
     out = {
-        "metric": PEEL_METRIC, "value": per["DG"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per["DG"]["seconds"] * 1e3, 4),
+        "metric": PEEL_METRIC, "value": per[lead]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per[lead]["seconds"] * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": dict(workload=args.workload, n=n, m=m, eps="1/10", k=2, metric="DG (DW, FD alongside)"),
+        "config": dict(workload=args.workload, n=n, m=m, eps="1/10", k=2,
+                       metric=lead + (" (%s alongside)" % ", ".join(metrics[1:]) if metrics[1:] else "")),
         "per_metric": per, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -291,6 +315,8 @@ def main():
     ap.add_argument("--plain", type=int, default=100, help="queries timed through the plain path")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--copy-probe-mb", type=int, default=0, help="also run a plain copy of this size")
+    ap.add_argument("--peel-metrics", default="DG,DW,FD",
+                    help="peeling inputs: metrics to run (the first gives value and roofline)")
     ap.add_argument("--serve", action="store_true", help="measure the serving loop instead of batches")
     ap.add_argument("--serve-sat", type=int, default=1024, help="queries for the saturation run")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each Poisson run")
@@ -427,11 +453,7 @@ def main():
                      p99_ms=round(float(np.percentile(lat, 99)), 4))
 
     if args.copy_probe_mb:
-        x = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
+        copy_probe(args.copy_probe_mb)
 
     cpu = None
     if args.cpu_budget > 0:

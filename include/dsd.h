@@ -87,12 +87,22 @@ typedef struct {
 /* Runs the peeling on the graph's device copy. Outputs (host memory, each
  * may be NULL):
  *   peel_round[n]           the round (1..R) in which each vertex was peeled;
- *                           S_best = { v : peel_round[v] > best }
+ *                           S_best = { v : peel_round[v] > best }. With NULL
+ *                           the rounds stay in device memory only (see
+ *                           kws_dsd_rounds)
  *   sizes[cap], f[cap]      |S_i| and f(S_i) for i = 0..R
  * KWS_EOVERFLOW if R + 1 > cap (with sizes or f given), KWS_EINVAL on bad
  * parameters, KWS_EDEVICE on a device failure. */
 kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel_round, int64_t *sizes,
                         int64_t *f, int32_t cap, kws_dsd_summary *summary);
+
+/* The peel rounds of the last finished kws_dsd_peel on g: copied into
+ * peel_round[n] (host memory) if it is not NULL, and the address of the
+ * library's device array of n int32 (on the device g was loaded on) stored
+ * in *device_rounds if that is not NULL. The device array is owned by g and
+ * holds these rounds until the next kws_dsd_peel or kws_dsd_free on g.
+ * KWS_EINVAL before the first run, KWS_EDEVICE on a device failure. */
+kws_status kws_dsd_rounds(kws_dsd_graph *g, int32_t *peel_round, const int32_t **device_rounds);
 
 #ifdef __cplusplus
 }

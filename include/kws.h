@@ -209,14 +209,17 @@ typedef struct {
 kws_status kws_autotune(kws_graph *g, const kws_query *sample, int32_t nq, int32_t reps, double budget_ms,
                         const char *cache_path, kws_options *best, kws_tune_report *report);
 
-/* Runs device work on this stream (a hipStream_t, e.g. from
- * torch.cuda.Stream().cuda_stream). NULL restores the handle's own stream.
- * The stream must be a default-priority stream. */
+/* Runs device work on this stream: a default-priority hipStream_t created
+ * through the same HIP runtime this library is linked against (ROCm's
+ * libamdhip64.so.7; a runtime bundled with another package, such as the
+ * copy inside a PyTorch wheel, is a separate runtime whose handles are not
+ * valid here). NULL restores the handle's own stream. */
 kws_status kws_set_stream(kws_graph *g, void *hip_stream);
 void *kws_get_stream(kws_graph *g);
 
-/* Device memory hooks (e.g. PyTorch's caching allocator). Process-wide;
- * set before loading graphs. alloc returns NULL on failure. NULL hooks
+/* Device memory hooks (a caller's own pool). Process-wide; set before
+ * loading graphs. alloc returns NULL on failure; the memory must come from
+ * the same HIP runtime as the library (see kws_set_stream). NULL hooks
  * restore hipMalloc/hipFree. */
 typedef void *(*kws_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*kws_free_fn)(void *ptr, void *ctx);

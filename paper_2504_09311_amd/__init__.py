@@ -5,6 +5,6 @@ The hot paths live in the HIP library ``libkws.so`` (C ABI in
 ``include/kws.h`` and ``include/dsd.h``); ``kws`` is its ctypes binding.
 """
 from .kws import (  # noqa: F401
-    Graph, Server, Result, PeelGraph, KwsError, load_library, declared_symbols, last_error, set_allocator_torch,
+    Graph, Server, Result, PeelGraph, KwsError, load_library, declared_symbols, last_error,
     OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EBUSY, ECANCELLED, MAX_KW, MAX_DMAX, MAX_K, DIST_INF,
 )

@@ -66,23 +66,33 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ s
 }
 
 // initial peeling weights: a_u plus the weights of all incident edges
-__global__ __launch_bounds__(BLOCK) void k_init_small(int32_t n, const int64_t *__restrict__ ptr,
-                                                      const int64_t *__restrict__ wt, const int64_t *__restrict__ a,
-                                                      int64_t *__restrict__ w, int32_t *__restrict__ rnd,
-                                                      int32_t *__restrict__ list) {
+// Peeling weights of the whole graph, w_u(V) = a_u + sum of the incident
+// edge weights; computed once at load (rows above SMALL_DEG are finished by
+// k_w0_big).
+__global__ __launch_bounds__(BLOCK) void k_w0_small(int32_t n, const int64_t *__restrict__ ptr,
+                                                    const int64_t *__restrict__ wt, const int64_t *__restrict__ a,
+                                                    int64_t *__restrict__ w0) {
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
     const int64_t b = ptr[v], e = ptr[v + 1];
     int64_t s = a ? a[v] : 0;
     if (!wt) s += e - b;
     else if (e - b <= SMALL_DEG)
       for (int64_t j = b; j < e; j++) s += wt[j];
-    w[v] = s;   // rows above SMALL_DEG are finished by k_init_big
+    w0[v] = s;
+  }
+}
+
+// start of a run: S_0 = V
+__global__ __launch_bounds__(BLOCK) void k_start(int32_t n, const int64_t *__restrict__ w0, int64_t *__restrict__ w,
+                                                 int32_t *__restrict__ rnd, int32_t *__restrict__ list) {
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
+    w[v] = w0[v];
     rnd[v] = ALIVE;
     list[v] = (int32_t)v;
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_init_big(const int32_t *__restrict__ big, int32_t nbig,
+__global__ __launch_bounds__(BLOCK) void k_w0_big(const int32_t *__restrict__ big, int32_t nbig,
                                                     const int64_t *__restrict__ ptr, const int64_t *__restrict__ wt,
                                                     int64_t *__restrict__ w) {
   const int lane = threadIdx.x & 63;
@@ -332,6 +342,7 @@ struct kws_dsd_graph {
   int64_t *a = nullptr;            // [n] vertex weights (FD only)
   int32_t *big = nullptr;          // vertices whose row is summed by a wavefront
   int32_t nbig = 0;
+  int64_t *w0 = nullptr;           // [n] peeling weights in G (start of every run)
   int64_t *w = nullptr;            // [n] peeling weights
   int32_t *rnd = nullptr;          // [n] round of removal
   int32_t *list[2] = {nullptr, nullptr};
@@ -339,6 +350,7 @@ struct kws_dsd_graph {
   kws::PeelScalars *sc = nullptr;
   int64_t *d_sizes = nullptr, *d_f = nullptr;
   int32_t d_cap = 0;
+  bool has_run = false;            // rnd holds the rounds of a finished run
   hipStream_t stream = nullptr;
 };
 
@@ -347,7 +359,7 @@ namespace {
 void dsd_release(kws_dsd_graph *g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
-  void *ps[] = {g->ptr, g->nbr, g->wt, g->a, g->big, g->w, g->rnd, g->list[0], g->list[1], g->ul, g->sc,
+  void *ps[] = {g->ptr, g->nbr, g->wt, g->a, g->big, g->w0, g->w, g->rnd, g->list[0], g->list[1], g->ul, g->sc,
                 g->d_sizes, g->d_f};
   for (void *p : ps) kws::dev_free(p);
   if (g->stream) (void)hipStreamDestroy(g->stream);
@@ -454,6 +466,7 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   if (d->metric != KWS_DSD_DG) DSD_STEP(dev_array(&g->wt, (size_t)(2 * m), "incidence weights"));
   if (d->metric == KWS_DSD_FD) DSD_STEP(dev_array(&g->a, (size_t)n, "vertex weights"));
   DSD_STEP(dev_array(&g->big, big.size(), "large rows"));
+  DSD_STEP(dev_array(&g->w0, (size_t)n, "initial peeling weights"));
   DSD_STEP(dev_array(&g->w, (size_t)n, "peeling weights"));
   DSD_STEP(dev_array(&g->rnd, (size_t)n, "peel rounds"));
   DSD_STEP(dev_array(&g->list[0], (size_t)n, "alive list"));
@@ -485,6 +498,10 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
                                                           g->nbr, g->wt);
     DSD_HIP(hipGetLastError());
   }
+  k_w0_small<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->ptr, g->wt, g->a, g->w0);
+  if (g->nbig && g->wt)
+    k_w0_big<<<grid_for((int64_t)g->nbig * 64, BLOCK, 65536), BLOCK, 0, s>>>(g->big, g->nbig, g->ptr, g->wt, g->w0);
+  DSD_HIP(hipGetLastError());
   DSD_HIP(hipStreamSynchronize(s));
   cleanup();
 #undef DSD_HIP
@@ -503,6 +520,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   if (p->k < 1 || p->k > 64 || p->eps_num < 0 || p->eps_num > 1000 || p->eps_den < 1 || p->eps_den > 1000)
     return fail(KWS_EINVAL, "k must be 1..64, eps_num 0..1000, eps_den 1..1000");
   if ((sizes || f) && cap < 1) return fail(KWS_EINVAL, "cap must be >= 1 with sizes or f");
+
   hipStream_t s = g->stream;
   const int32_t n = g->n;
   // device record of the rounds: enough for eps > 0 at any size; more is
@@ -521,9 +539,9 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   const bool prof = p->profile != 0;
   const int64_t resident = 2048;
   KWS_HIP(hipGetLastError());
+  g->has_run = false;
   k_scalars_init<<<1, 64, 0, s>>>(g->sc, n);
-  k_init_small<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->ptr, g->wt, g->a, g->w, g->rnd, g->list[0]);
-  if (g->nbig && g->wt) k_init_big<<<grid_for((int64_t)g->nbig * 64, BLOCK, 65536), BLOCK, 0, s>>>(g->big, g->nbig, g->ptr, g->wt, g->w);
+  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd, g->list[0]);
   {
     DsdTimer t(prof, s, &sum.reduce_ms, &sum.reduce_launches);
     k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
@@ -570,7 +588,8 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   std::vector<int64_t> hs((size_t)round + 1), hf((size_t)round + 1);
   KWS_HIP(hipMemcpyAsync(hs.data(), g->d_sizes, sizeof(int64_t) * hs.size(), hipMemcpyDeviceToHost, s));
   KWS_HIP(hipMemcpyAsync(hf.data(), g->d_f, sizeof(int64_t) * hf.size(), hipMemcpyDeviceToHost, s));
-  if (peel_round) KWS_HIP(hipMemcpyAsync(peel_round, g->rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+  if (peel_round && n > 0)
+    KWS_HIP(hipMemcpyAsync(peel_round, g->rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
   KWS_HIP(hipStreamSynchronize(s));
   int32_t R = 0;
   while (R < round && hs[R] > 0) R++;
@@ -583,6 +602,20 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   sum.best_f = h.best_i < 0 ? 0 : h.best_f;
   sum.incidences = 2 * g->m;   // every vertex is peeled once: each edge is visited from both ends
   if (summary) *summary = sum;
+  g->has_run = true;
+  return KWS_OK;
+}
+
+kws_status kws_dsd_rounds(kws_dsd_graph *g, int32_t *peel_round, const int32_t **device_rounds) {
+  using namespace kws;
+  clear_error();
+  if (!g) return fail(KWS_EINVAL, "null graph");
+  if (!g->has_run) return fail(KWS_EINVAL, "no finished peeling run on this graph");
+  if (device_rounds) *device_rounds = g->rnd;
+  if (peel_round && g->n > 0) {
+    KWS_HIP(hipMemcpyAsync(peel_round, g->rnd, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost, g->stream));
+    KWS_HIP(hipStreamSynchronize(g->stream));
+  }
   return KWS_OK;
 }
 

@@ -173,6 +173,7 @@ def load_library(path: str = LIB_PATH):
         "kws_dsd_load": (C.c_int, [C.POINTER(DsdDesc), C.POINTER(P)]),
         "kws_dsd_free": (None, [P]),
         "kws_dsd_peel": (C.c_int, [P, C.POINTER(DsdParams), P, P, P, C.c_int32, C.POINTER(DsdSummary)]),
+        "kws_dsd_rounds": (C.c_int, [P, P, C.POINTER(P)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -483,28 +484,6 @@ class Server:
             pass
 
 
-_torch_hooks = None
-
-
-def set_allocator_torch(device: int = 0):
-    """Route the library's device allocations through PyTorch's caching allocator."""
-    import torch
-    global _torch_hooks
-
-    def _alloc(nbytes, ctx):
-        try:
-            return int(torch.cuda.caching_allocator_alloc(int(nbytes), device))
-        except Exception:
-            return None
-
-    def _free(ptr, ctx):
-        torch.cuda.caching_allocator_delete(int(ptr))
-
-    _torch_hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
-    _check(load_library().kws_set_allocator(C.cast(_torch_hooks[0], C.c_void_p),
-                                            C.cast(_torch_hooks[1], C.c_void_p), None))
-
-
 class PeelGraph:
     """Densest-subgraph discovery by parallel peeling (wraps include/dsd.h)."""
     METRICS = {"DG": 0, "DW": 1, "FD": 2}
@@ -524,19 +503,35 @@ class PeelGraph:
         _check(lib.kws_dsd_load(C.byref(d), C.byref(h)))
         self.h = h
 
-    def peel(self, k: int = 2, eps_num: int = 1, eps_den: int = 10, profile: bool = False, cap: int = 0):
-        """(peel_round[n], sizes[R+1], f[R+1], summary dict) of one run."""
+    def peel(self, k: int = 2, eps_num: int = 1, eps_den: int = 10, profile: bool = False, cap: int = 0,
+             rounds: bool = True):
+        """(peel_round[n], sizes[R+1], f[R+1], summary dict) of one run.
+
+        rounds=False leaves the peel rounds in device memory (None is
+        returned in their place; ``rounds()`` fetches them later)."""
         cap = cap or 65536
-        pr = np.empty(max(self.n, 1), np.int32)
         sizes = np.empty(cap, np.int64)
         fs = np.empty(cap, np.int64)
         sm = DsdSummary()
+        pr = np.empty(max(self.n, 1), np.int32) if rounds else None
         p = DsdParams(k, eps_num, eps_den, 1 if profile else 0)
-        _check(self._lib.kws_dsd_peel(self.h, C.byref(p), pr.ctypes.data, sizes.ctypes.data, fs.ctypes.data, cap,
-                                      C.byref(sm)))
+        _check(self._lib.kws_dsd_peel(self.h, C.byref(p), pr.ctypes.data if rounds else None, sizes.ctypes.data,
+                                      fs.ctypes.data, cap, C.byref(sm)))
         R = int(sm.rounds)
-        return pr[:self.n].copy(), sizes[:R + 1].copy(), fs[:R + 1].copy(), \
+        return (pr[:self.n].copy() if rounds else None), sizes[:R + 1].copy(), fs[:R + 1].copy(), \
             {k2: getattr(sm, k2) for k2, _ in sm._fields_}
+
+    def rounds(self) -> np.ndarray:
+        """Peel rounds of the last run, copied from device memory."""
+        pr = np.empty(max(self.n, 1), np.int32)
+        _check(self._lib.kws_dsd_rounds(self.h, pr.ctypes.data, None))
+        return pr[:self.n].copy()
+
+    def device_rounds(self) -> int:
+        """Device address of the last run's peel rounds (n int32, owned by the graph)."""
+        d = C.c_void_p()
+        _check(self._lib.kws_dsd_rounds(self.h, None, C.byref(d)))
+        return d.value or 0
 
     def close(self):
         if getattr(self, "h", None):

@@ -122,3 +122,19 @@ def test_rmat24_full_scale_certified(K):
         assert R - 1 < math.log(n) / math.log(1.1)
         say("certifying rounds", sorted({1, 2, R // 2, R}))
         certify(n, src, dst, c, a, 2, 1, 10, pr, sizes, fs, sm["best"], sorted({1, 2, R // 2, R}))
+
+
+
+def test_rounds_left_on_device(K):
+    inp = workloads.peel_input("peel_rmat20", scale=14)
+    n = inp["n"]
+    for metric in oracle.METRICS:
+        G = K.PeelGraph(n, inp["src"], inp["dst"], metric, edge_w=inp["edge_w"], vertex_w=inp["vertex_w"])
+        with pytest.raises(K.KwsError):
+            G.rounds()                                   # no run yet
+        pr, sizes, fs, sm = G.peel(2, 1, 10)
+        none, sizes_d, fs_d, sm_d = G.peel(2, 1, 10, rounds=False)
+        assert none is None and np.array_equal(G.rounds(), pr), metric
+        assert np.array_equal(sizes_d, sizes) and np.array_equal(fs_d, fs) and sm_d["best"] == sm["best"], metric
+        assert G.device_rounds() != 0
+        G.close()

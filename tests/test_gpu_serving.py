@@ -124,6 +124,29 @@ def test_graph_replay_matches(K, rmat14):
     G.set_options()
 
 
+def test_caller_stream(K, rmat14):
+    """Work on a stream the caller created through the library's own HIP runtime."""
+    import ctypes
+    g, o, G = rmat14
+    hip = ctypes.CDLL("libamdhip64.so.7")          # the instance libkws.so is linked against
+    st = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(st)) == 0
+    try:
+        qs = workloads.rmat_flat_queries(32, 2, 6, [2, 3], 10, cfg=2, qcfg=8)
+        want = oracle_results(o, qs)
+        G.set_stream(st.value)
+        assert G.get_stream() == st.value
+        say("caller stream")
+        assert_all_same(G.search_batch(qs), want, "caller stream")
+        assert_same(G.keyword_search(qs[0].kw, qs[0].d_max, qs[0].k), want[0], "caller stream, one query")
+        G.set_stream(None)
+        assert G.get_stream() not in (0, st.value)
+        assert_all_same(G.search_batch(qs), want, "own stream again")
+    finally:
+        G.set_stream(None)
+        hip.hipStreamDestroy(st)
+
+
 def test_pipelined_batches(K, rmat14):
     g, o, G = rmat14
     qa = workloads.rmat_flat_queries(64, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=6)
