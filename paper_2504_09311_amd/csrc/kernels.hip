@@ -160,6 +160,12 @@ __global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass P) {
 // vertices per round and loads the words of up to 8 / VU tiles of each before
 // any store, so every thread has 8 independent load pairs in flight whatever
 // the tile count (VU is 8 / min(tiles, 8), rounded to a power of two).
+// Distance plane b (bit b of each lane's distance) is stored outright at the
+// word's level 2^b, the first level that sets that bit: every lane not new
+// there has a distance without bit b or none yet. Later levels with bit b
+// OR their arrivals in. With S.clear_planes (words that may stop before
+// level 2^b, as in the server) planes are cleared when the word starts and
+// every level ORs.
 template <int T, int VU>
 __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) {
   extern __shared__ uint64_t s_live[];                    // [Wp]
@@ -167,6 +173,11 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
   constexpr int TG = 8 / VU;              // tiles per load group
   const int tid = threadIdx.x, gl = tid & (G - 1), lane = tid & 63;
   const uint64_t gmask = group_bits(lane, G);
+  uint64_t *__restrict__ vis = P.vis;
+  uint64_t *__restrict__ nxt = P.nxt;
+  uint64_t *__restrict__ planes = P.planes;
+  uint64_t *__restrict__ frn = S.fr_next;
+  const size_t ps = P.pstride;
   for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
   __syncthreads();
   uint64_t live_acc[TG];                  // lanes with new frontier in the first TG tiles
@@ -186,8 +197,8 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
         for (int k = 0; k < TG; k++) {
           const bool ok = v[u] < P.n && t0 + k < P.tiles;
           const size_t idx = ((size_t)(t0 + k) * P.n + v[u]) * T + gl;
-          nxv[u][k] = ok ? __builtin_nontemporal_load(&P.nxt[idx]) : 0ull;
-          oldv[u][k] = ok ? __builtin_nontemporal_load(&P.vis[idx]) : 0ull;
+          nxv[u][k] = ok ? __builtin_nontemporal_load(&nxt[idx]) : 0ull;
+          oldv[u][k] = ok ? __builtin_nontemporal_load(&vis[idx]) : 0ull;
         }
 #pragma unroll
       for (int k = 0; k < TG; k++) {
@@ -195,29 +206,35 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
         const int j = (t0 + k) * T + gl;
         const int nl = S.newlvl[j];
         const uint64_t an = S.act_new[j], ann = S.act_nn[j];
+        // planes OR-ed into at this level: every bit of nl, except the bit
+        // of a power-of-two level when planes are stored there outright
+        const bool first_store = !S.clear_planes;
+        const int rmw = first_store && (nl & (nl - 1)) == 0 ? 0 : nl;
         uint64_t lacc = 0;
 #pragma unroll
         for (int u = 0; u < VU; u++) {
           if (v[u] >= P.n) continue;
           const size_t idx = ((size_t)(t0 + k) * P.n + v[u]) * T + gl;
-          const uint64_t nx = nxv[u][k];
           const uint64_t old = nl ? oldv[u][k] : 0ull;
-          const uint64_t fnew = nx & ~old & an;
+          const uint64_t fnew = nxv[u][k] & ~old & an;
           const uint64_t nv = old | fnew;
           if (nl == 0) {
-            P.vis[idx] = nv;
-            for (int b = 0; b < P.B; b++) P.planes[b * P.pstride + idx] = 0;
-          } else if (fnew) {
-            P.vis[idx] = nv;
-            for (int b = 0; b < P.B; b++)
-              if ((nl >> b) & 1) P.planes[b * P.pstride + idx] |= fnew;
+            vis[idx] = nv;
+            if (S.clear_planes)
+              for (int b = 0; b < P.B; b++) planes[b * ps + idx] = 0;
+          } else {
+            if (fnew) vis[idx] = nv;
+            for (int b = 0; b < P.B; b++) {
+              if (first_store && nl == (1 << b)) planes[b * ps + idx] = fnew;
+              else if (fnew && ((rmw >> b) & 1)) planes[b * ps + idx] |= fnew;
+            }
           }
           if (S.write_next) {
-            __builtin_nontemporal_store(fnew, &S.fr_next[idx]);
+            __builtin_nontemporal_store(fnew, &frn[idx]);
             lacc |= fnew;
             anyneed[u] |= ann & ~nv;
           }
-          if (nx) __builtin_nontemporal_store(0ull, &P.nxt[idx]);
+          if (nxv[u][k]) __builtin_nontemporal_store(0ull, &nxt[idx]);
           anyf[u] |= fnew;
         }
         if (t0 == 0) live_acc[k] |= lacc;

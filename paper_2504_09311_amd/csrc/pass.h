@@ -85,6 +85,8 @@ struct Step {
   uint64_t *live_out;        // [Wp]
   int32_t build_list;        // write the frontier list (a following push reads it)
   int32_t write_next;        // write fr_next and live_out
+  int32_t clear_planes;      // clear the distance planes when a word starts; otherwise every
+                             // word reaches level 2^b for every plane b, where b is stored
 };
 
 kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof);

@@ -216,6 +216,7 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
   S.live_out = live + (size_t)(1 - par) * wstride;
   S.build_list = 1;
   S.write_next = 1;
+  S.clear_planes = 1;   // a slot's word stops at its own d_max
   // the step's output statistics are cleared with the counters
   KWS_HIP(hipMemsetAsync(S.st_out, 0, STAT_WORDS * sizeof(uint64_t), s->stream));
   KWS_TRY(launch_seed(P, s->stream, s->prof));
