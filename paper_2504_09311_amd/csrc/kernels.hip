@@ -469,8 +469,10 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
 // offset, d_max, query id, in word order), the chunk's histogram and the te
 // sums live in LDS, so the query loop issues no global load and the
 // histogram adds are LDS atomics; without L (batches too large for LDS)
-// the same loop reads the tables from global memory and adds there.
-template <int T, bool L>
+// the same loop reads the tables from global memory and adds there. TE
+// (count_te) is a template argument so that the query loop carries no te
+// work when it is off; the loop bounds are wavefront-uniform scalars.
+template <int T, bool L, bool TE>
 __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;                                   // [nq] (count_te)
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
     const int64_t cend = min((int64_t)P.n, (int64_t)(c + 1) * P.CH);
     const int64_t v = (int64_t)c * P.CH + (int64_t)part * BLOCK + tid;
     const bool valid = v < cend;
-    const uint64_t indeg = (valid && P.count_te) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
+    const uint64_t indeg = (TE && valid) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
     const int32_t *wqp = L ? s_wqp : P.word_q_ptr;
     constexpr int H = T < 8 ? T : 8;      // words held in registers at a time
     for (int tile = 0; tile < P.tiles; tile++) {
@@ -549,36 +551,46 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
 #pragma unroll
         for (int w = 0; w < H; w++) {
           const int j = tile * T + h0 + w;
-          const int qb = wqp[j], qe = wqp[j + 1];
+          const int qb = __builtin_amdgcn_readfirstlane(wqp[j]), qe = __builtin_amdgcn_readfirstlane(wqp[j + 1]);
           if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
-          for (int qi = qb; qi < qe; qi++) {
-            const uint64_t m = L ? s_qm[qi] : P.q_mask[P.word_q[qi]];
-            const bool root = valid && (m & ~vis[w]) == 0;
-            if (P.count_te) {
-              const int q = L ? s_qx[qi] : P.word_q[qi];
-              const int dq = L ? s_qd[qi] : P.q_dmax[q];
-              const uint64_t x = vis[w] & m;
-              uint64_t eq = x;
+          // the masks of four queries are read before any of them is tested
+          for (int q0 = qb; q0 < qe; q0 += 4) {
+            uint64_t m4[4];
 #pragma unroll
-              for (int b = 0; b < 4; b++)
-                if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
-              uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
-              if (__ballot(t != 0)) {
-                for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-                if (lane == 0) {
-                  if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
-                  else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
+            for (int k4 = 0; k4 < 4; k4++)
+              m4[k4] = q0 + k4 < qe ? (L ? s_qm[q0 + k4] : P.q_mask[P.word_q[q0 + k4]]) : ~0ull;
+#pragma unroll
+            for (int k4 = 0; k4 < 4; k4++) {
+              const int qi = q0 + k4;
+              if (qi >= qe) break;
+              const uint64_t m = m4[k4];
+              const bool root = valid && (m & ~vis[w]) == 0;
+              if (TE) {
+                const int q = L ? s_qx[qi] : P.word_q[qi];
+                const int dq = L ? s_qd[qi] : P.q_dmax[q];
+                const uint64_t x = vis[w] & m;
+                uint64_t eq = x;
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                  if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
+                uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
+                if (__ballot(t != 0)) {
+                  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+                  if (lane == 0) {
+                    if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
+                    else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
+                  }
                 }
               }
-            }
-            if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
-            int sc = __popcll(pl[0][w] & m);
+              if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
+              int sc = __popcll(pl[0][w] & m);
 #pragma unroll
-            for (int b = 1; b < 4; b++)
-              if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
-            if (root) {
-              if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
-              else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
+              for (int b = 1; b < 4; b++)
+                if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
+              if (root) {
+                if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
+                else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
+              }
             }
           }
         }
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
         if (s_hist[i]) atomicAdd(&P.hist[(size_t)c * P.nhist + i], s_hist[i]);
     __syncthreads();
   }
-  if (L && P.count_te) {
+  if (L && TE) {
     __syncthreads();
     for (int i = tid; i < P.nq; i += BLOCK)
       if (s_te[i]) atomicAdd((unsigned long long *)&P.te[s_qx[i]], (unsigned long long)s_te[i]);
@@ -988,11 +1000,14 @@ kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
   {
     Timer t(prof, s, KC_SCORE);
     const int64_t split = (P.CH + BLOCK - 1) / BLOCK;
+    const int grid = clamp_grid(P.chunks * split);
     if (P.hist_lds) {
       const size_t lds = (size_t)P.nq * (8 + 8 + 4 + 4 + 4) + sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist);
-      k_score<T, true><<<clamp_grid(P.chunks * split), BLOCK, lds, s>>>(P);
+      if (P.count_te) k_score<T, true, true><<<grid, BLOCK, lds, s>>>(P);
+      else k_score<T, true, false><<<grid, BLOCK, lds, s>>>(P);
     } else {
-      k_score<T, false><<<clamp_grid(P.chunks * split), BLOCK, 0, s>>>(P);
+      if (P.count_te) k_score<T, false, true><<<grid, BLOCK, 0, s>>>(P);
+      else k_score<T, false, false><<<grid, BLOCK, 0, s>>>(P);
     }
   }
   KWS_TRY(launch_check("score"));
