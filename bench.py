@@ -63,14 +63,15 @@ def make_workload(name: str, scale: int | None, nq: int | None):
     return g, qs, desc
 
 
-def byte_model(st: dict, n: int, kernel: str) -> float:
+def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0) -> float:
     """Algorithmic bytes of all launches of one kernel class in one step.
 
     expansion (push or pull) of level l, with U_l the frontier vertices,
     E_l their in-edges and T_l the vertices that gain a lane (= U_{l+1}),
     W the 64-lane words: 8|U_l| + 4E_l + 8W|U_l| + 16W|T_l|.
     finalize: one streaming pass over n*Wp words reading nxt and vis and
-    writing the next frontier: 24 bytes per vertex-word and level.
+    writing the next frontier: 24 bytes per vertex-word and launch (one per
+    level; level 0 has none when seeding by vertex, which writes it itself).
     score: 8*W*n*(1 + planes).
     """
     W, Wp, L = st["words"], st["words_padded"], st["levels"]
@@ -84,7 +85,7 @@ def byte_model(st: dict, n: int, kernel: str) -> float:
             tot += 8 * f[lv] + 4 * fe[lv] + 8 * W * f[lv] + 16 * W * f[lv + 1]
         return tot
     if kernel == "finalize":
-        return 24.0 * n * Wp * (L + 1)
+        return 24.0 * n * Wp * launches
     if kernel == "score":
         planes = max(1, int(np.ceil(np.log2(L + 1)))) if L > 0 else 0
         return 8.0 * W * n * (1 + planes)
@@ -416,7 +417,8 @@ def main():
     kernels = {k: dict(launches=v[0], total_ms=round(v[1], 4),
                        avg_us=round(v[1] * 1e3 / v[0], 3) if v[0] else 0.0)
                for k, v in prof.items() if v[0]}
-    modeled = {k: byte_model(st, g.n, k) for k in ("pull", "push", "finalize", "score")}
+    modeled = {k: byte_model(st, g.n, k, kernels.get(k, {}).get("launches", 0) / args.steps)
+               for k in ("pull", "push", "finalize", "score")}
     roofline = None
     if kernels:
         cand = [k for k in modeled if k in kernels and modeled[k] > 0]

@@ -150,6 +150,106 @@ __global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass P) {
   }
 }
 
+// ---- the per-pass counters, zeroed before a seeding kernel that adds to
+// some of them (k_seed_level0)
+__global__ __launch_bounds__(BLOCK) void k_zero_pass(const Pass P) {
+  const int64_t gid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, gsz = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
+  for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
+  for (int64_t i = gid; i < P.zero2_words; i += gsz) P.zero2[i] = 0;
+}
+
+// ---- seeding by vertex fused with the finalize of level 0 (batched passes,
+// where every word starts at level 0): the lookups of k_seed_vertex, then
+// each vertex's row is its level-0 frontier, so it goes to vis and to the
+// first frontier buffer directly (nxt is not touched), together with the
+// frontier flag, the level-0 statistics and the live lanes that
+// k_finalize would have produced from it.
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass P, const Step S) {
+  extern __shared__ uint64_t s_rows[];   // [VB][Wp + 1] rows, [Wp] live lanes, [VB] vertex flags
+  const int tid = threadIdx.x, lane = tid & 63, VB = P.seed_vb, SUB = BLOCK / VB, RS = P.Wp + 1;
+  uint64_t *s_live = s_rows + (size_t)VB * RS;
+  uint32_t *s_vf = (uint32_t *)(s_live + P.Wp);
+  const int vl = tid / SUB, sub = tid % SUB;
+  const uint32_t hmask = (uint32_t)P.hcap - 1;
+  uint64_t nf_acc = 0, mf_acc = 0, mu_acc = 0;
+  for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
+  for (int64_t v0 = (int64_t)blockIdx.x * VB; v0 < P.n; v0 += (int64_t)gridDim.x * VB) {
+    for (int i = tid; i < VB * RS; i += BLOCK) s_rows[i] = 0;
+    for (int i = tid; i < VB; i += BLOCK) s_vf[i] = 0;
+    __syncthreads();
+    const int64_t v = v0 + vl;
+    if (v < P.n) {
+      uint64_t *row = s_rows + (size_t)vl * RS;
+      const int32_t a = P.lab_ptr[v], b = P.lab_ptr[v + 1];
+      for (int32_t i = a; i < b; i++) {
+        for (int32_t t = P.lab[i]; t >= 0; t = P.tparent ? P.tparent[t] : -1) {
+          uint32_t h = ((uint32_t)t * 2654435761u) & hmask;
+          int32_t key;
+          while ((key = P.h_key[h]) != t && key != -1) h = (h + 1) & hmask;
+          if (key != t) continue;
+          const int32_t e0 = P.h_beg[h], e1 = e0 + P.h_cnt[h];
+          for (int32_t e = e0 + sub; e < e1; e += SUB)
+            atomicOr((unsigned long long *)&row[P.e_word[e]], (unsigned long long)P.e_mask[e]);
+        }
+      }
+    }
+    __syncthreads();
+    const int nv = (int)min((int64_t)VB, (int64_t)P.n - v0);
+    // per vertex: bit 0 any frontier lane, bit 1 a lane still to reach at level 1
+    if (vl < nv) {
+      const uint64_t *row = s_rows + (size_t)vl * RS;
+      uint32_t fl = 0;
+      for (int j = sub; j < P.W; j += SUB) {
+        const uint64_t m = row[j];
+        if (m) fl |= 1u;
+        if (S.act_nn[j] & ~m) fl |= 2u;
+      }
+      if (fl) atomicOr(&s_vf[vl], fl);
+    }
+    for (int tile = 0; tile < P.tiles; tile++) {
+      uint64_t lacc = 0;                  // every thread keeps one word (tid % T) of the tile
+      for (int r = tid; r < VB * T; r += BLOCK) {
+        const int u = r / T, w = r % T;
+        if (u >= nv) break;
+        const uint64_t m = s_rows[(size_t)u * RS + tile * T + w];
+        const size_t idx = ((size_t)tile * P.n + v0 + u) * T + w;
+        __builtin_nontemporal_store(m, &P.vis[idx]);
+        if (S.write_next) __builtin_nontemporal_store(m, &S.fr_next[idx]);
+        lacc |= m;
+      }
+      if (S.write_next) {
+        for (int off = T; off < 64; off <<= 1) lacc |= __shfl_xor(lacc, off);
+        if (lane < T && lacc) atomicOr((unsigned long long *)&s_live[tile * T + lane], lacc);
+      }
+    }
+    __syncthreads();
+    if (sub == 0 && vl < nv) {
+      const uint32_t fl = s_vf[vl];
+      if (S.build_list) S.flags_next[v] = (fl & 1u) ? 1 : 0;
+      if (fl & 1u) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
+      if ((fl & 2u) && S.write_next) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
+    }
+    __syncthreads();
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nf_acc += __shfl_xor(nf_acc, off);
+    mf_acc += __shfl_xor(mf_acc, off);
+    mu_acc += __shfl_xor(mu_acc, off);
+  }
+  if (lane == 0) {
+    uint64_t *st = stat_stripe(S.st_out, blockIdx.x);
+    if (nf_acc) atomicAdd((unsigned long long *)&st[0], (unsigned long long)((nf_acc << 32) | mf_acc));
+    if (mu_acc) atomicAdd((unsigned long long *)&st[1], (unsigned long long)mu_acc);
+  }
+  if (S.write_next) {
+    __syncthreads();
+    for (int j = tid; j < P.Wp; j += BLOCK)
+      if (s_live[j]) atomicOr((unsigned long long *)&S.live_out[j], s_live[j]);
+  }
+}
+
 // ---- finalize one step: new = nxt & ~vis & act_new; vis |= new; distance
 // planes; next frontier buffer; nxt cleared; a frontier flag per vertex;
 // the statistics that pick the direction of the next level (frontier size,
@@ -1076,6 +1176,25 @@ kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
       case 16: k_seed<16><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
       default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
     }
+  }
+  return launch_check("seed");
+}
+
+kws_status launch_seed_level0(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
+  Timer t(prof, s, KC_SEED);
+  const int64_t zwords = std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words));
+  if (zwords > 0) k_zero_pass<<<clamp_grid((zwords + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P);
+  const int64_t vblocks = ((int64_t)P.n + P.seed_vb - 1) / P.seed_vb;
+  const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(vblocks, 1), 4096));
+  const size_t lds = sizeof(uint64_t) * ((size_t)P.seed_vb * (size_t)(P.Wp + 1) + (size_t)P.Wp) +
+                     sizeof(uint32_t) * (size_t)P.seed_vb;
+  switch (P.T) {
+    case 1: k_seed_level0<1><<<grid, BLOCK, lds, s>>>(P, S); break;
+    case 2: k_seed_level0<2><<<grid, BLOCK, lds, s>>>(P, S); break;
+    case 4: k_seed_level0<4><<<grid, BLOCK, lds, s>>>(P, S); break;
+    case 8: k_seed_level0<8><<<grid, BLOCK, lds, s>>>(P, S); break;
+    case 16: k_seed_level0<16><<<grid, BLOCK, lds, s>>>(P, S); break;
+    default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
   }
   return launch_check("seed");
 }

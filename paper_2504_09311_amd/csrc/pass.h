@@ -90,6 +90,9 @@ struct Step {
 };
 
 kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof);
+// Seeding by vertex and the finalize of level 0 in one kernel (batched
+// passes: every word starts at level 0; S is the level-0 step).
+kws_status launch_seed_level0(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
 kws_status launch_expand(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
 kws_status launch_finalize(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
 kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof);

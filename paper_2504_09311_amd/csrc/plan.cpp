@@ -324,7 +324,10 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   // vertices per block round of the vertex seeding: rows of Wp + 1 words in
   // at most 64 KB of LDS
   P.seed_vb = BLOCK;
-  while (P.seed_vb > 1 && (size_t)P.seed_vb * (size_t)(P.Wp + 1) * 8 > 65536) P.seed_vb >>= 1;
+  // rows of Wp + 1 words, plus the live lanes and one flag per vertex of
+  // the fused level-0 seeding, within 64 KB of LDS
+  while (P.seed_vb > 1 && ((size_t)P.seed_vb * (size_t)(P.Wp + 1) + (size_t)P.Wp) * 8 + (size_t)P.seed_vb * 4 > 65536)
+    P.seed_vb >>= 1;
   P.q_mask = (const uint64_t *)(dp + qo.mask);
   P.q_word = (const int32_t *)(dp + qo.word);
   P.q_dmax = (const int32_t *)(dp + qo.dmax);

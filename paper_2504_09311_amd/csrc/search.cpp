@@ -19,8 +19,12 @@ constexpr kws_status PASS_TOO_WIDE = (kws_status)1;   // internal: retry with fe
 // Device work of one pass: seed, D levels, finish.
 kws_status launch_pass(kws_graph *g, const Pass &P, const std::vector<Step> &steps) {
   hipStream_t s = g->stream;
-  KWS_TRY(launch_seed(P, s, g->prof));
-  KWS_TRY(launch_finalize(P, steps[0], s, g->prof));
+  if (P.seed_by_vertex) {
+    KWS_TRY(launch_seed_level0(P, steps[0], s, g->prof));
+  } else {
+    KWS_TRY(launch_seed(P, s, g->prof));
+    KWS_TRY(launch_finalize(P, steps[0], s, g->prof));
+  }
   for (size_t i = 1; i < steps.size(); i++) {
     KWS_TRY(launch_expand(P, steps[i], s, g->prof));
     KWS_TRY(launch_finalize(P, steps[i], s, g->prof));
