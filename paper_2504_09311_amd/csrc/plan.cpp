@@ -177,10 +177,11 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
   for (int j = 0; j < Wp; j++) wq_ptr[j + 1] += wq_ptr[j];
   std::vector<int32_t> fill(wq_ptr.begin(), wq_ptr.end() - 1);
   for (int i = 0; i < nq; i++) wq[fill[word[i]]++] = i;
-  // chunks of at most 8192 vertices (the select step scans whole chunks),
-  // at least 2048, and no more than 4096 of them (histograms per chunk)
-  chunks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, std::max<int64_t>(((int64_t)n + 8191) / 8192,
-                                                                              std::min<int64_t>(512, ((int64_t)n + 2047) / 2048))));
+  // chunks of about 1024 vertices (the select step scans whole chunks for
+  // the few that hold a selected root), as long as the histograms (one
+  // int per chunk and histogram bin) stay within 512 MB
+  const int64_t hist_cap = std::max<int64_t>(1, ((int64_t)1 << 27) / std::max<int64_t>(1, nhist));
+  chunks = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n + 1023) / 1024, hist_cap));
   CH = (int)align_up((size_t)((n + chunks - 1) / chunks), 64);
   chunks = (n + CH - 1) / CH;
   // the score step keeps the query table (28 bytes per query), the word ->
