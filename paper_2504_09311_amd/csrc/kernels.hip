@@ -880,6 +880,7 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
   __shared__ int32_t s_best;
+  __shared__ int32_t s_samp[BLOCK];
   const int tid = threadIdx.x;
   for (int64_t item = blockIdx.x; item < P.total_kd; item += gridDim.x) {
     int lo = 0, hi = P.nq;                      // query owning this (root, keyword) item
@@ -905,11 +906,22 @@ __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
       int32_t best = 0x7fffffff;
       if (d == 1 && ns * 4 < (int64_t)(e1 - e0)) {
         // last hop: the keyword's vertices are few compared with the row, so
-        // look each of them up in the sorted row and keep the smallest hit
+        // look each of them up in the sorted row and keep the smallest hit:
+        // first among BLOCK evenly spaced samples of the row held in LDS,
+        // then within the one segment between two samples
+        const int32_t len = e1 - e0, step = (len + BLOCK - 1) / BLOCK, nsamp = (len + step - 1) / step;
+        for (int k = tid; k < nsamp; k += BLOCK) s_samp[k] = P.fwd_col[e0 + (int64_t)k * step];
+        __syncthreads();
         int32_t mine = 0x7fffffff;
         for (int64_t k = tid; k < ns; k += BLOCK) {
           const int32_t v = P.inv_vtx[sb + k];
-          int32_t a = e0, b = e1;
+          if (s_samp[0] > v) continue;
+          int32_t lo = 0, hi = nsamp;        // last sample <= v
+          while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (s_samp[mid] <= v) lo = mid; else hi = mid;
+          }
+          int32_t a = e0 + lo * step, b = min(e1, a + step);
           while (a < b) {
             const int32_t mid = (a + b) >> 1;
             if (P.fwd_col[mid] < v) a = mid + 1; else b = mid;
