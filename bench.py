@@ -72,7 +72,8 @@ def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0) -> float:
     finalize: one streaming pass over n*Wp words reading nxt and vis and
     writing the next frontier: 24 bytes per vertex-word and launch (one per
     level; level 0 has none when seeding by vertex, which writes it itself).
-    score: 8*W*n*(1 + planes).
+    score: 8*W*n*(2 + planes) (vis, the planes and, for the last level's
+    arrivals it merges, nxt).
     """
     W, Wp, L = st["words"], st["words_padded"], st["levels"]
     f, fe, pulled = st["frontier"], st["frontier_edges"], st["pulled"]
@@ -88,7 +89,7 @@ def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0) -> float:
         return 24.0 * n * Wp * launches
     if kernel == "score":
         planes = max(1, int(np.ceil(np.log2(L + 1)))) if L > 0 else 0
-        return 8.0 * W * n * (1 + planes)
+        return 8.0 * W * n * (2 + planes)
     return 0.0
 
 

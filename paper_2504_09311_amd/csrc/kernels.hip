@@ -7,6 +7,7 @@
 // The push/pull choice is made on the device from the statistics the
 // previous finalize wrote, so the launch sequence never depends on data.
 #include <algorithm>
+#include <cstring>
 
 #include <map>
 #include <mutex>
@@ -572,8 +573,12 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
 // the same loop reads the tables from global memory and adds there. TE
 // (count_te) is a template argument so that the query loop carries no te
 // work when it is off; the loop bounds are wavefront-uniform scalars.
-template <int T, bool L, bool TE>
-__global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
+// With FIN the kernel also does the finalize of the last level (step F, in
+// a batched pass, where nothing follows that level): it reads nxt beside
+// vis and the planes, merges the arrivals in registers, writes back only
+// what changed, clears nxt and adds the level's frontier statistics.
+template <int T, bool L, bool TE, bool FIN>
+__global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;                                   // [nq] (count_te)
   uint64_t *s_qm = s_dyn + P.nq;                            // [nq] masks in word order
@@ -595,6 +600,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
       s_qx[i] = q;
     }
   }
+  uint64_t nf_acc = 0, mf_acc = 0;        // FIN: frontier of the last level
   for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
     const int c = (int)(bid / split), part = (int)(bid % split);
     if (L)
@@ -606,6 +612,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
     const uint64_t indeg = (TE && valid) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
     const int32_t *wqp = L ? s_wqp : P.word_q_ptr;
     constexpr int H = T < 8 ? T : 8;      // words held in registers at a time
+    bool anyf = false;
     for (int tile = 0; tile < P.tiles; tile++) {
 #pragma unroll 1
       for (int h0 = 0; h0 < T; h0 += H) {
@@ -639,6 +646,34 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
 #pragma unroll
             for (int b = 0; b < 4; b++)
               if (b < P.B) pl[b][0] = P.planes[b * P.pstride + base];
+          }
+          if (FIN) {
+            // the last level's arrivals; words without a query have no lane
+            // and so nothing in nxt
+#pragma unroll
+            for (int w = 0; w < H; w++) {
+              const int j = tile * T + h0 + w;
+              const int nl = F.newlvl[j];
+              const uint64_t nx = __builtin_nontemporal_load(&P.nxt[base + w]);
+              const uint64_t fnew = nx & ~vis[w] & F.act_new[j];
+              if (fnew) {
+                vis[w] |= fnew;
+                P.vis[base + w] = vis[w];
+                anyf = true;
+              }
+#pragma unroll
+              for (int b = 0; b < 4; b++)
+                if (b < P.B) {
+                  if (nl == (1 << b)) {                    // first level with bit b: stored outright
+                    pl[b][w] = fnew;
+                    P.planes[b * P.pstride + base + w] = fnew;
+                  } else if (fnew && ((nl >> b) & 1)) {
+                    pl[b][w] |= fnew;
+                    P.planes[b * P.pstride + base + w] = pl[b][w];
+                  }
+                }
+              if (nx) __builtin_nontemporal_store(0ull, &P.nxt[base + w]);
+            }
           }
 #pragma unroll
           for (int w = 0; w < H; w++)
@@ -696,6 +731,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
         }
       }
     }
+    if (FIN && anyf) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
     __syncthreads();
     if (L)
       for (int i = tid; i < P.nhist; i += BLOCK)
@@ -706,6 +742,14 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P) {
     __syncthreads();
     for (int i = tid; i < P.nq; i += BLOCK)
       if (s_te[i]) atomicAdd((unsigned long long *)&P.te[s_qx[i]], (unsigned long long)s_te[i]);
+  }
+  if (FIN) {
+    for (int off = 32; off > 0; off >>= 1) {
+      nf_acc += __shfl_xor(nf_acc, off);
+      mf_acc += __shfl_xor(mf_acc, off);
+    }
+    if (lane == 0 && nf_acc)
+      atomicAdd((unsigned long long *)stat_stripe(F.st_out, blockIdx.x), (unsigned long long)((nf_acc << 32) | mf_acc));
   }
 }
 
@@ -1106,20 +1150,33 @@ kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &pro
   return launch_check("finalize");
 }
 
+template <int T, bool TE, bool FIN>
+void score_launch(const Pass &P, const Step &F, int grid, size_t lds, hipStream_t s) {
+  if (P.hist_lds) k_score<T, true, TE, FIN><<<grid, BLOCK, lds, s>>>(P, F);
+  else k_score<T, false, TE, FIN><<<grid, BLOCK, 0, s>>>(P, F);
+}
+
 template <int T>
-kws_status finish_t(const Pass &P, hipStream_t s, Profiler &prof) {
-  if (P.nq == 0) return KWS_OK;
+kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &prof) {
+  if (P.nq == 0) {
+    if (last) return launch_finalize(P, *last, s, prof);   // nothing to score: a plain finalize
+    return KWS_OK;
+  }
   {
     Timer t(prof, s, KC_SCORE);
     const int64_t split = (P.CH + BLOCK - 1) / BLOCK;
     const int grid = clamp_grid(P.chunks * split);
-    if (P.hist_lds) {
-      const size_t lds = (size_t)P.nq * (8 + 8 + 4 + 4 + 4) + sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist);
-      if (P.count_te) k_score<T, true, true><<<grid, BLOCK, lds, s>>>(P);
-      else k_score<T, true, false><<<grid, BLOCK, lds, s>>>(P);
+    const size_t lds = P.hist_lds ? (size_t)P.nq * (8 + 8 + 4 + 4 + 4) +
+                                        sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist)
+                                  : 0;
+    Step none;
+    std::memset(&none, 0, sizeof(none));
+    if (last) {
+      if (P.count_te) score_launch<T, true, true>(P, *last, grid, lds, s);
+      else score_launch<T, false, true>(P, *last, grid, lds, s);
     } else {
-      if (P.count_te) k_score<T, false, true><<<grid, BLOCK, 0, s>>>(P);
-      else k_score<T, false, false><<<grid, BLOCK, 0, s>>>(P);
+      if (P.count_te) score_launch<T, true, false>(P, none, grid, lds, s);
+      else score_launch<T, false, false>(P, none, grid, lds, s);
     }
   }
   KWS_TRY(launch_check("score"));
@@ -1219,8 +1276,8 @@ kws_status launch_finalize(const Pass &P, const Step &S, hipStream_t s, Profiler
   KWS_DISPATCH_T(P.T, finalize_t<TT>(P, S, s, prof))
 }
 
-kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof) {
-  KWS_DISPATCH_T(P.T, finish_t<TT>(P, s, prof))
+kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof, const Step *last) {
+  KWS_DISPATCH_T(P.T, finish_t<TT>(P, last, s, prof))
 }
 
 kws_status launch_export(const Pass &P, uint8_t *out, hipStream_t s) {

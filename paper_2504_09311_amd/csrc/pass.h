@@ -95,7 +95,9 @@ kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof);
 kws_status launch_seed_level0(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
 kws_status launch_expand(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
 kws_status launch_finalize(const Pass &P, const Step &S, hipStream_t s, Profiler &prof);
-kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof);
+// Score, rank and answer; with last, the score kernel also does the
+// finalize of that step (the last level of a batched pass).
+kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof, const Step *last = nullptr);
 kws_status launch_export(const Pass &P, uint8_t *out, hipStream_t s);
 kws_status launch_fill_zero(uint64_t *p, size_t words, hipStream_t s);
 

@@ -25,11 +25,17 @@ kws_status launch_pass(kws_graph *g, const Pass &P, const std::vector<Step> &ste
     KWS_TRY(launch_seed(P, s, g->prof));
     KWS_TRY(launch_finalize(P, steps[0], s, g->prof));
   }
+  // With tiles of at most 8 words a score thread holds a vertex's whole
+  // tile row, so the score kernel does the last level's finalize (its
+  // stores fill whole lines); wider tiles keep the separate pass, where the
+  // stores of the merge would be scattered partial lines.
+  const Step *last = nullptr;
   for (size_t i = 1; i < steps.size(); i++) {
     KWS_TRY(launch_expand(P, steps[i], s, g->prof));
-    KWS_TRY(launch_finalize(P, steps[i], s, g->prof));
+    if (i + 1 < steps.size() || P.T > 8) KWS_TRY(launch_finalize(P, steps[i], s, g->prof));
+    else last = &steps[i];
   }
-  return launch_finish(P, s, g->prof);
+  return launch_finish(P, s, g->prof, last);
 }
 
 // The same work through a hipGraph captured once per pass shape (the key
