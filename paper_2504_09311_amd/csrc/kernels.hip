@@ -754,16 +754,36 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
 }
 
 // ---- threshold: per query, the score s* of the k-th root, how many ties at
-// s* to take, and one work item per chunk that holds a selected root.
-__global__ __launch_bounds__(BLOCK) void k_threshold(const Pass P) {
+// s* to take, and one work item per chunk that holds a selected root. A
+// block of TH_BLOCK threads per query (a query's histograms span every
+// chunk, and the ranks of ties run over the chunks in order).
+constexpr int TH_BLOCK = 1024;
+
+__device__ int32_t th_block_scan(int32_t x, int32_t *total) {
+  __shared__ int32_t s_w[TH_BLOCK / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int32_t incl = wave_incl_scan(x, lane);
+  if (lane == 63) s_w[wid] = incl;
+  __syncthreads();
+  int32_t base = 0, all = 0;
+  for (int w = 0; w < TH_BLOCK / 64; w++) {
+    base += w < wid ? s_w[w] : 0;
+    all += s_w[w];
+  }
+  __syncthreads();
+  *total = all;
+  return base + incl - x;
+}
+
+__global__ __launch_bounds__(TH_BLOCK) void k_threshold(const Pass P) {
   __shared__ int32_t tot[KWS_MAX_KW * KWS_MAX_DMAX + 1];
   __shared__ int32_t s_sel[4];
   const int tid = threadIdx.x;
   for (int q = blockIdx.x; q < P.nq; q += gridDim.x) {
     const int S1 = P.q_nk[q] * P.q_dmax[q] + 1, hoff = P.q_hoff[q];
-    for (int s = tid; s < S1; s += BLOCK) tot[s] = 0;
+    for (int s = tid; s < S1; s += TH_BLOCK) tot[s] = 0;
     __syncthreads();
-    for (int64_t i = tid; i < (int64_t)P.chunks * S1; i += BLOCK) {
+    for (int64_t i = tid; i < (int64_t)P.chunks * S1; i += TH_BLOCK) {
       const int c = (int)(i / S1), s = (int)(i % S1);
       const int32_t h = P.hist[(size_t)c * P.nhist + hoff + s];
       if (h) atomicAdd(&tot[s], h);
@@ -788,7 +808,7 @@ __global__ __launch_bounds__(BLOCK) void k_threshold(const Pass P) {
     const int32_t keff = s_sel[0], sstar = s_sel[1], need = s_sel[2];
     if (keff > 0) {
       int32_t carry = 0;
-      for (int base = 0; base < P.chunks; base += BLOCK) {
+      for (int base = 0; base < P.chunks; base += TH_BLOCK) {
         const int c = base + tid;
         int32_t t = 0, lt = 0;
         if (c < P.chunks) {
@@ -797,7 +817,7 @@ __global__ __launch_bounds__(BLOCK) void k_threshold(const Pass P) {
           for (int s = 0; s < sstar; s++) lt += h[s];
         }
         int32_t btot;
-        const int32_t ex = block_scan(t, &btot) + carry;
+        const int32_t ex = th_block_scan(t, &btot) + carry;
         carry += btot;
         if (c < P.chunks && (lt > 0 || (t > 0 && ex < need))) {
           const int32_t pos = atomicAdd(P.work_cnt, 1);
@@ -912,6 +932,8 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const Pass P) {
 // the smallest-id out-neighbour one hop closer, writing the path into the
 // keyword's segment of the root's edge slot; then one wave per (query, root)
 // merges the segments: sort, drop repeats.
+constexpr int AB = 256;   // threads per answer walk (neighbours scanned per round)
+
 __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
   if ((threadIdx.x & 63) == 0) atomicMin(slot, v);
@@ -922,9 +944,9 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
 }
 
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
+__global__ __launch_bounds__(AB) void k_answer(const Pass P) {
   __shared__ int32_t s_best;
-  __shared__ int32_t s_samp[BLOCK];
+  __shared__ int32_t s_samp[AB];
   const int tid = threadIdx.x;
   for (int64_t item = blockIdx.x; item < P.total_kd; item += gridDim.x) {
     int lo = 0, hi = P.nq;                      // query owning this (root, keyword) item
@@ -951,13 +973,13 @@ __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
       if (d == 1 && ns * 4 < (int64_t)(e1 - e0)) {
         // last hop: the keyword's vertices are few compared with the row, so
         // look each of them up in the sorted row and keep the smallest hit:
-        // first among BLOCK evenly spaced samples of the row held in LDS,
+        // first among AB evenly spaced samples of the row held in LDS,
         // then within the one segment between two samples
-        const int32_t len = e1 - e0, step = (len + BLOCK - 1) / BLOCK, nsamp = (len + step - 1) / step;
-        for (int k = tid; k < nsamp; k += BLOCK) s_samp[k] = P.fwd_col[e0 + (int64_t)k * step];
+        const int32_t len = e1 - e0, step = (len + AB - 1) / AB, nsamp = (len + step - 1) / step;
+        for (int k = tid; k < nsamp; k += AB) s_samp[k] = P.fwd_col[e0 + (int64_t)k * step];
         __syncthreads();
         int32_t mine = 0x7fffffff;
-        for (int64_t k = tid; k < ns; k += BLOCK) {
+        for (int64_t k = tid; k < ns; k += AB) {
           const int32_t v = P.inv_vtx[sb + k];
           if (s_samp[0] > v) continue;
           int32_t lo = 0, hi = nsamp;        // last sample <= v
@@ -976,14 +998,14 @@ __global__ __launch_bounds__(BLOCK) void k_answer(const Pass P) {
       } else {
         // rows are sorted by neighbour id, so the qualifying neighbours of
         // the first round that has any include the smallest-id one; most
-        // walks stop in their first round of BLOCK neighbours, so rounds are
+        // walks stop in their first round of AB neighbours, so rounds are
         // not made longer
         constexpr int U = 1;
-        for (int32_t eb = e0; eb < e1; eb += BLOCK * U) {
+        for (int32_t eb = e0; eb < e1; eb += AB * U) {
           int32_t y[U], mine = 0x7fffffff;
 #pragma unroll
           for (int u = 0; u < U; u++) {
-            const int32_t e = eb + u * BLOCK + tid;
+            const int32_t e = eb + u * AB + tid;
             y[u] = e < e1 ? P.fwd_col[e] : -1;
           }
 #pragma unroll
@@ -1182,7 +1204,7 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
   KWS_TRY(launch_check("score"));
   {
     Timer t(prof, s, KC_THRESHOLD);
-    k_threshold<<<clamp_grid(P.nq), BLOCK, 0, s>>>(P);
+    k_threshold<<<clamp_grid(P.nq), TH_BLOCK, 0, s>>>(P);
   }
   KWS_TRY(launch_check("threshold"));
   {
@@ -1198,7 +1220,7 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
   {
     Timer t(prof, s, KC_ANSWER);
     const int64_t waves = BLOCK / 64;
-    k_answer<T><<<clamp_grid(P.total_kd), BLOCK, 0, s>>>(P);
+    k_answer<T><<<clamp_grid(P.total_kd), AB, 0, s>>>(P);
     k_answer_merge<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
   }
   return launch_check("answer");
