@@ -577,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
 // a batched pass, where nothing follows that level): it reads nxt beside
 // vis and the planes, merges the arrivals in registers, writes back only
 // what changed, clears nxt and adds the level's frontier statistics.
-template <int T, bool L, bool TE, bool FIN>
+template <int T, bool L, bool TE, bool FIN, int PB>
 __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;                                   // [nq] (count_te)
@@ -611,18 +611,21 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
     const bool valid = v < cend;
     const uint64_t indeg = (TE && valid) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
     const int32_t *wqp = L ? s_wqp : P.word_q_ptr;
-    constexpr int H = T < 8 ? T : 8;      // words held in registers at a time
+    // words held in registers at a time: a whole 16-word row when at most
+    // two planes are used (the row's lines are then read once; in halves,
+    // they are mostly evicted before the second half is read)
+    constexpr int H = (T == 16 && PB == 2) ? 16 : (T < 8 ? T : 8);
     bool anyf = false;
     for (int tile = 0; tile < P.tiles; tile++) {
 #pragma unroll 1
       for (int h0 = 0; h0 < T; h0 += H) {
         if (wqp[tile * T + h0] == wqp[tile * T + h0 + H]) continue;   // no query in these words
         const size_t base = ((size_t)tile * P.n + (valid ? v : 0)) * T + h0;
-        uint64_t vis[H], pl[4][H];
+        uint64_t vis[H], pl[PB][H];
 #pragma unroll
         for (int w = 0; w < H; w++) vis[w] = 0ull;
 #pragma unroll
-        for (int b = 0; b < 4; b++)
+        for (int b = 0; b < PB; b++)
 #pragma unroll
           for (int w = 0; w < H; w++) pl[b][w] = 0ull;
         if (valid) {
@@ -634,7 +637,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
               vis[w] = x.x; vis[w + 1 < H ? w + 1 : w] = H >= 2 ? x.y : x.x;
             }
 #pragma unroll
-            for (int b = 0; b < 4; b++)
+            for (int b = 0; b < PB; b++)
               if (b < P.B)
 #pragma unroll
                 for (int w = 0; w < H; w += 2) {
@@ -644,7 +647,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
           } else {
             vis[0] = P.vis[base];
 #pragma unroll
-            for (int b = 0; b < 4; b++)
+            for (int b = 0; b < PB; b++)
               if (b < P.B) pl[b][0] = P.planes[b * P.pstride + base];
           }
           if (FIN) {
@@ -662,7 +665,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
                 anyf = true;
               }
 #pragma unroll
-              for (int b = 0; b < 4; b++)
+              for (int b = 0; b < PB; b++)
                 if (b < P.B) {
                   if (nl == (1 << b)) {                    // first level with bit b: stored outright
                     pl[b][w] = fnew;
@@ -680,7 +683,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
             if (tile * T + h0 + w >= P.W) {   // padding words carry no lane
               vis[w] = 0ull;
 #pragma unroll
-              for (int b = 0; b < 4; b++) pl[b][w] = 0ull;
+              for (int b = 0; b < PB; b++) pl[b][w] = 0ull;
             }
         }
 #pragma unroll
@@ -706,7 +709,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
                 const uint64_t x = vis[w] & m;
                 uint64_t eq = x;
 #pragma unroll
-                for (int b = 0; b < 4; b++)
+                for (int b = 0; b < PB; b++)
                   if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
                 uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
                 if (__ballot(t != 0)) {
@@ -720,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
               if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
               int sc = __popcll(pl[0][w] & m);
 #pragma unroll
-              for (int b = 1; b < 4; b++)
+              for (int b = 1; b < PB; b++)
                 if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
               if (root) {
                 if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
@@ -932,8 +935,6 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const Pass P) {
 // the smallest-id out-neighbour one hop closer, writing the path into the
 // keyword's segment of the root's edge slot; then one wave per (query, root)
 // merges the segments: sort, drop repeats.
-constexpr int AB = 256;   // threads per answer walk (neighbours scanned per round)
-
 __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
   if ((threadIdx.x & 63) == 0) atomicMin(slot, v);
@@ -943,7 +944,10 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
   return r;
 }
 
-template <int T>
+// AB threads per walk scan AB neighbours per round: 512 when a pass has few
+// walks (wider rounds end long rows sooner), 256 when it has many (more
+// walks in flight).
+template <int T, int AB>
 __global__ __launch_bounds__(AB) void k_answer(const Pass P) {
   __shared__ int32_t s_best;
   __shared__ int32_t s_samp[AB];
@@ -1172,10 +1176,19 @@ kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &pro
   return launch_check("finalize");
 }
 
+// 16-word tiles with at most two planes hold whole rows (PB = 2); every
+// other shape keeps room for four planes and rows of at most 8 words
 template <int T, bool TE, bool FIN>
 void score_launch(const Pass &P, const Step &F, int grid, size_t lds, hipStream_t s) {
-  if (P.hist_lds) k_score<T, true, TE, FIN><<<grid, BLOCK, lds, s>>>(P, F);
-  else k_score<T, false, TE, FIN><<<grid, BLOCK, 0, s>>>(P, F);
+  if constexpr (T == 16) {
+    if (P.B <= 2) {
+      if (P.hist_lds) k_score<T, true, TE, FIN, 2><<<grid, BLOCK, lds, s>>>(P, F);
+      else k_score<T, false, TE, FIN, 2><<<grid, BLOCK, 0, s>>>(P, F);
+      return;
+    }
+  }
+  if (P.hist_lds) k_score<T, true, TE, FIN, 4><<<grid, BLOCK, lds, s>>>(P, F);
+  else k_score<T, false, TE, FIN, 4><<<grid, BLOCK, 0, s>>>(P, F);
 }
 
 template <int T>
@@ -1220,7 +1233,8 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
   {
     Timer t(prof, s, KC_ANSWER);
     const int64_t waves = BLOCK / 64;
-    k_answer<T><<<clamp_grid(P.total_kd), AB, 0, s>>>(P);
+    if (P.total_kd <= 16384) k_answer<T, 512><<<clamp_grid(P.total_kd), 512, 0, s>>>(P);
+    else k_answer<T, 256><<<clamp_grid(P.total_kd), 256, 0, s>>>(P);
     k_answer_merge<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
   }
   return launch_check("answer");
