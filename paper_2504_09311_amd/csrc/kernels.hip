@@ -259,8 +259,9 @@ __global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass P, const Step 
 // frontier list a push needs is built by k_compact, only for levels that push.
 // T threads per vertex (one per word of a tile); each thread takes VU
 // vertices per round and loads the words of up to 8 / VU tiles of each before
-// any store, so every thread has 8 independent load pairs in flight whatever
-// the tile count (VU is 8 / min(tiles, 8), rounded to a power of two).
+// any store, so every thread has up to 8 independent load pairs in flight
+// (VU is 8 / min(tiles, 8), rounded to a power of two, and at most 4: with
+// one tile, 4 vertices per thread leave room for more resident waves).
 // Distance plane b (bit b of each lane's distance) is stored outright at the
 // word's level 2^b, the first level that sets that bit: every lane not new
 // there has a distance without bit b or none yet. Later levels with bit b
@@ -1155,7 +1156,7 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
 
 template <int T>
 kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
-  const int vu = P.tiles >= 8 ? 1 : P.tiles >= 4 ? 2 : P.tiles >= 2 ? 4 : 8;
+  const int vu = P.tiles >= 8 ? 1 : P.tiles >= 4 ? 2 : 4;
   const int64_t per_block = (int64_t)(BLOCK / T) * vu;
   const size_t lds = sizeof(uint64_t) * (size_t)P.Wp;
   // one round of resident blocks that stride over the vertices: a second,
