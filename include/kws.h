@@ -245,6 +245,12 @@ kws_status kws_graph_info_get(kws_graph *g, kws_graph_info *info);
  * host wall time per batch pass: planning and plan upload, kernel enqueue,
  * waiting for the device, unpacking the results. */
 kws_status kws_profile_enable(kws_graph *g, int32_t on);
+/* Kernel classes bracketed by events while profiling is on: bit id of mask
+ * for class id (the default, and mask 0, time every class). Events add a
+ * little device time per launch, so timing only the class being measured
+ * keeps the rest of the run at full speed. Host-phase classes are always
+ * counted (they use no events). */
+kws_status kws_profile_classes(kws_graph *g, uint64_t mask);
 kws_status kws_profile_reset(kws_graph *g);
 kws_status kws_profile_read(kws_graph *g, int32_t id, int64_t *launches, double *total_ms);
 const char *kws_profile_name(int32_t id);

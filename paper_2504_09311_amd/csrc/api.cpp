@@ -157,9 +157,8 @@ hipEvent_t Profiler::get() {
 }
 
 void Profiler::begin(int cls, hipStream_t s, hipEvent_t *a) {
-  (void)cls;
   *a = nullptr;
-  if (!on) return;
+  if (!on || !((mask >> cls) & 1ull)) return;
   *a = get();
   if (*a) hipEventRecord(*a, s);
 }
@@ -399,6 +398,13 @@ kws_status kws_profile_enable(kws_graph *g, int32_t on) {
   if (!g) return kws::fail(KWS_EINVAL, "null graph");
   std::lock_guard<std::mutex> lk(g->mu);
   g->prof.on = on != 0;
+  return KWS_OK;
+}
+
+kws_status kws_profile_classes(kws_graph *g, uint64_t mask) {
+  if (!g) return kws::fail(KWS_EINVAL, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->prof.mask = mask ? mask : ~0ull;
   return KWS_OK;
 }
 

@@ -66,6 +66,7 @@ const char *kernel_class_name(int id);
 
 struct Profiler {
   bool on = false;
+  uint64_t mask = ~0ull;                // classes bracketed by events
   struct Pending { int cls; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;

@@ -157,6 +157,7 @@ def load_library(path: str = LIB_PATH):
         "kws_graph_info_get": (C.c_int, [P, C.POINTER(GraphInfo)]),
         "kws_profile_enable": (C.c_int, [P, C.c_int32]),
         "kws_profile_reset": (C.c_int, [P]),
+        "kws_profile_classes": (C.c_int, [P, C.c_uint64]),
         "kws_profile_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "kws_profile_name": (C.c_char_p, [C.c_int32]),
         "kws_last_batch_stats": (C.c_int, [P, C.POINTER(BatchStats)]),
@@ -408,6 +409,22 @@ class Graph:
 
     def profile_reset(self):
         _check(self._lib.kws_profile_reset(self.h))
+
+    def profile_classes(self, names=None):
+        """Time only these kernel classes with events (None: every class)."""
+        mask = 0
+        if names:
+            ids = {}
+            i = 0
+            while True:
+                nm = self._lib.kws_profile_name(i)
+                if not nm:
+                    break
+                ids[nm.decode()] = i
+                i += 1
+            for n in names:
+                mask |= 1 << ids[n]
+        _check(self._lib.kws_profile_classes(self.h, mask))
 
     def profile_read(self) -> dict:
         out = {}
