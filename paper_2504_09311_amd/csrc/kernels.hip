@@ -653,30 +653,51 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
           }
           if (FIN) {
             // the last level's arrivals; words without a query have no lane
-            // and so nothing in nxt
+            // and so nothing in nxt. The row is updated in registers and
+            // written back whole (16-byte stores) where it changed.
+            bool rowf = false, rown = false;
+            uint32_t store_pl = 0;                 // planes whose row is written
 #pragma unroll
             for (int w = 0; w < H; w++) {
               const int j = tile * T + h0 + w;
               const int nl = F.newlvl[j];
               const uint64_t nx = __builtin_nontemporal_load(&P.nxt[base + w]);
               const uint64_t fnew = nx & ~vis[w] & F.act_new[j];
+              rown |= nx != 0;
               if (fnew) {
                 vis[w] |= fnew;
-                P.vis[base + w] = vis[w];
-                anyf = true;
+                rowf = true;
               }
 #pragma unroll
               for (int b = 0; b < PB; b++)
                 if (b < P.B) {
                   if (nl == (1 << b)) {                    // first level with bit b: stored outright
                     pl[b][w] = fnew;
-                    P.planes[b * P.pstride + base + w] = fnew;
+                    store_pl |= 1u << b;
                   } else if (fnew && ((nl >> b) & 1)) {
                     pl[b][w] |= fnew;
-                    P.planes[b * P.pstride + base + w] = pl[b][w];
+                    store_pl |= 1u << b;
                   }
                 }
-              if (nx) __builtin_nontemporal_store(0ull, &P.nxt[base + w]);
+            }
+            if (rowf) anyf = true;
+            if (H >= 2) {
+#pragma unroll
+              for (int w = 0; w < H; w += 2) {
+                if (rowf) *(ulonglong2 *)(P.vis + base + w) = make_ulonglong2(vis[w], vis[w + 1 < H ? w + 1 : w]);
+#pragma unroll
+                for (int b = 0; b < PB; b++)
+                  if ((store_pl >> b) & 1u)
+                    *(ulonglong2 *)(P.planes + b * P.pstride + base + w) =
+                        make_ulonglong2(pl[b][w], pl[b][w + 1 < H ? w + 1 : w]);
+                if (rown) *(ulonglong2 *)(P.nxt + base + w) = make_ulonglong2(0ull, 0ull);
+              }
+            } else {
+              if (rowf) P.vis[base] = vis[0];
+#pragma unroll
+              for (int b = 0; b < PB; b++)
+                if ((store_pl >> b) & 1u) P.planes[b * P.pstride + base] = pl[b][0];
+              if (rown) P.nxt[base] = 0ull;
             }
           }
 #pragma unroll

@@ -110,6 +110,12 @@ def test_server_null_arguments():
     lib.kws_batch_result_free(None)
 
 
+def test_profile_classes_needs_a_graph():
+    import ctypes as C
+    lib = K.load_library()
+    assert lib.kws_profile_classes(None, C.c_uint64(1)) == K.EINVAL
+
+
 def test_dsd_load_rejects_bad_input():
     # validation happens on the host before any device call
     lib = K.load_library()

@@ -147,6 +147,27 @@ def test_caller_stream(K, rmat14):
         hip.hipStreamDestroy(st)
 
 
+def test_profile_class_mask(K, rmat14):
+    g, o, G = rmat14
+    qs = workloads.rmat_flat_queries(32, 2, 6, [2, 3], 10, cfg=2, qcfg=9)
+    want = oracle_results(o, qs)
+    G.profile_classes(["pull", "score"])
+    G.profile_enable(True)
+    G.profile_reset()
+    assert_all_same(G.search_batch(qs), want, "profiled, two classes")
+    G.profile_enable(False)
+    prof = G.profile_read()
+    assert prof["score"][0] >= 1 and prof["seed"][0] == 0 and prof["finalize"][0] == 0 and prof["answer"][0] == 0
+    assert prof["host_plan"][0] >= 1                      # host phases use no events
+    G.profile_classes(None)
+    G.profile_enable(True)
+    G.profile_reset()
+    assert_all_same(G.search_batch(qs), want, "profiled, every class")
+    G.profile_enable(False)
+    prof = G.profile_read()
+    assert prof["seed"][0] >= 1 and prof["score"][0] >= 1 and prof["answer"][0] >= 1
+
+
 def test_pipelined_batches(K, rmat14):
     g, o, G = rmat14
     qa = workloads.rmat_flat_queries(64, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=6)
