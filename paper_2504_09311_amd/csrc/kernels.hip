@@ -972,7 +972,8 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
 template <int T, int AB>
 __global__ __launch_bounds__(AB) void k_answer(const Pass P) {
   __shared__ int32_t s_best;
-  __shared__ int32_t s_samp[AB];
+  constexpr int NSAMP = 4096;             // row samples held in LDS for the last hop
+  __shared__ int32_t s_samp[NSAMP];
   const int tid = threadIdx.x;
   for (int64_t item = blockIdx.x; item < P.total_kd; item += gridDim.x) {
     int lo = 0, hi = P.nq;                      // query owning this (root, keyword) item
@@ -999,9 +1000,10 @@ __global__ __launch_bounds__(AB) void k_answer(const Pass P) {
       if (d == 1 && ns * 4 < (int64_t)(e1 - e0)) {
         // last hop: the keyword's vertices are few compared with the row, so
         // look each of them up in the sorted row and keep the smallest hit:
-        // first among AB evenly spaced samples of the row held in LDS,
-        // then within the one segment between two samples
-        const int32_t len = e1 - e0, step = (len + AB - 1) / AB, nsamp = (len + step - 1) / step;
+        // first among NSAMP evenly spaced samples of the row held in LDS
+        // (the whole row when it is that short), then within the one
+        // segment between two samples
+        const int32_t len = e1 - e0, step = (len + NSAMP - 1) / NSAMP, nsamp = (len + step - 1) / step;
         for (int k = tid; k < nsamp; k += AB) s_samp[k] = P.fwd_col[e0 + (int64_t)k * step];
         __syncthreads();
         int32_t mine = 0x7fffffff;
@@ -1013,12 +1015,14 @@ __global__ __launch_bounds__(AB) void k_answer(const Pass P) {
             const int32_t mid = (lo + hi) >> 1;
             if (s_samp[mid] <= v) lo = mid; else hi = mid;
           }
-          int32_t a = e0 + lo * step, b = min(e1, a + step);
+          if (s_samp[lo] == v) { mine = min(mine, v); continue; }
+          const int32_t seg_end = min(e1, e0 + lo * step + step);   // v lies after sample lo, before the next
+          int32_t a = e0 + lo * step + 1, b = seg_end;
           while (a < b) {
             const int32_t mid = (a + b) >> 1;
             if (P.fwd_col[mid] < v) a = mid + 1; else b = mid;
           }
-          if (a < e1 && P.fwd_col[a] == v) mine = min(mine, v);
+          if (a < seg_end && P.fwd_col[a] == v) mine = min(mine, v);
         }
         best = block_min(mine, &s_best);
       } else {
