@@ -60,6 +60,10 @@ def _bind(lib):
     lib.orc_peel.restype = C.c_int
     lib.orc_peel.argtypes = [C.c_int32, C.c_int64, i32p, i32p, i64p, i64p, C.c_int32, C.c_int32, C.c_int32,
                              i32p, i64p, i64p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.orc_peel_opt.restype = C.c_int
+    lib.orc_peel_opt.argtypes = [C.c_int32, C.c_int64, i32p, i32p, i64p, i64p, C.c_int32, C.c_int32, C.c_int32,
+                                 C.c_int32, i32p, i64p, i64p, C.c_int32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.orc_peel_sequential.restype = C.c_int
     lib.orc_peel_sequential.argtypes = [C.c_int32, C.c_int64, i32p, i32p, i64p, i64p, u8p,
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -231,6 +235,34 @@ def peel(n: int, src, dst, c, a, k: int = 2, eps_num: int = 1, eps_den: int = 10
         raise ValueError(f"orc_peel failed ({st})")
     R = int(r.value)
     return PeelResult(pr[:n].copy(), sizes[:R + 1].copy(), fs[:R + 1].copy(), R, int(b.value))
+
+
+PEEL_MODES = {"plain": 0, "gpo": 1, "lpo": 2}
+
+
+def peel_opt(n: int, src, dst, c, a, k: int = 2, eps_num: int = 1, eps_den: int = 10, mode: str = "lpo",
+             cap: int = 0) -> PeelResult:
+    """Peeling with the global threshold (gpo, Algorithm 3) and the local
+    trimming loop (lpo, Algorithm 4) (peel_oracle.c: orc_peel_opt); the
+    result's ``trims`` attribute counts the trimming steps."""
+    lib = load()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    c = np.ascontiguousarray(c, np.int64)
+    a = np.ascontiguousarray(a, np.int64)
+    cap = cap or n + 2
+    pr = np.empty(max(n, 1), np.int32)
+    sizes = np.empty(cap, np.int64)
+    fs = np.empty(cap, np.int64)
+    r, b, t = C.c_int32(), C.c_int32(), C.c_int32()
+    st = lib.orc_peel_opt(n, src.shape[0], src, dst, c, a, k, eps_num, eps_den, PEEL_MODES[mode], pr, sizes, fs,
+                          cap, C.byref(r), C.byref(b), C.byref(t))
+    if st != 0:
+        raise ValueError(f"orc_peel_opt failed ({st})")
+    R = int(r.value)
+    res = PeelResult(pr[:n].copy(), sizes[:R + 1].copy(), fs[:R + 1].copy(), R, int(b.value))
+    res.trims = int(t.value)
+    return res
 
 
 def peel_sequential(n: int, src, dst, c, a):

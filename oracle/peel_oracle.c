@@ -19,6 +19,10 @@
  *            S_i = S_{i-1} \ U
  *   result  the first i in 0..R with the largest g(S_i) over non-empty S_i.
  *
+ * orc_peel_opt adds the long-tail optimisations of Section 5: the global
+ * peeling threshold (Algorithm 3) and the local trimming loop
+ * (Algorithm 4), in the same from-scratch style.
+ *
  * Metric weights (Section 2.1 and the example listing of Section 3):
  *   DG  a_u = 0,  c_e = 1
  *   DW  a_u = 0,  c_e = the given edge weight
@@ -150,5 +154,115 @@ int orc_peel_sequential(int32_t n, int64_t m, const int32_t *src, const int32_t 
   *bf_out = bf;
   *bs_out = bs;
   free(alive); free(order); free(w);
+  return 0;
+}
+
+/* f(S) and the peeling weights w_u(S) of every u in S, from the definitions;
+ * S = { u : peel_round[u] == PEEL_ALIVE }. */
+static int64_t opt_weights(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *c,
+                           const int64_t *a, const int32_t *peel_round, int64_t *w) {
+  int64_t f = 0;
+  for (int32_t u = 0; u < n; u++) {
+    w[u] = a[u];
+    if (peel_round[u] == PEEL_ALIVE) f += a[u];
+  }
+  for (int64_t e = 0; e < m; e++)
+    if (peel_round[src[e]] == PEEL_ALIVE && peel_round[dst[e]] == PEEL_ALIVE) {
+      f += c[e];
+      w[src[e]] += c[e];
+      w[dst[e]] += c[e];
+    }
+  return f;
+}
+
+/*
+ * Peeling with the long-tail optimisations of Section 5. mode 1 is the
+ * global peeling threshold of Algorithm 3 (GPO), mode 2 adds the local
+ * trimming loop of Algorithm 4 (LPO); mode 0 is Algorithm 2 (as orc_peel).
+ * tau_max starts at 0. Outer iteration i, with S = S_{i-1}:
+ *   modes 1, 2: tau_max = max(tau_max, g(S) / (k (1 + eps)))
+ *   U1 = { u in S : w_u(S) <= max(tau_max, k (1 + eps) g(S)) },  S = S \ U1
+ *   mode 2: while some u in S has w_u(S) < g(S):
+ *             U2 = { u in S : w_u(S) < max(tau_max, g(S)) },  S = S \ U2
+ *   S_i = S; every vertex removed in iteration i (by U1 or a U2) gets peel
+ *   round i.
+ * The result is the first i in 0..R with the largest g(S_i) over non-empty
+ * S_i (S_i after its trimming). tau_max is kept as a fraction A / B and
+ * every comparison is cross-multiplied in 128 bits. Outputs as orc_peel,
+ * plus *trims (the number of trimming steps). Returns 0, -1 on bad input,
+ * -2 if more than cap - 1 iterations would be needed.
+ */
+int orc_peel_opt(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int64_t *c, const int64_t *a,
+                 int32_t k, int32_t eps_num, int32_t eps_den, int32_t mode, int32_t *peel_round, int64_t *sizes,
+                 int64_t *fs, int32_t cap, int32_t *rounds, int32_t *best, int32_t *trims) {
+  if (n < 0 || m < 0 || k < 1 || eps_num < 0 || eps_den < 1 || cap < 1 || mode < 0 || mode > 2) return -1;
+  for (int64_t e = 0; e < m; e++)
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n || src[e] == dst[e] || c[e] < 0) return -1;
+  for (int32_t u = 0; u < n; u++)
+    if (a[u] < 0) return -1;
+  int64_t *w = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!w) return -1;
+  for (int32_t u = 0; u < n; u++) peel_round[u] = PEEL_ALIVE;
+  const u128 K1 = (u128)(uint64_t)k * (u128)(uint64_t)(eps_den + eps_num);   /* k (1 + eps) = K1 / den */
+  const u128 den = (u128)(uint64_t)eps_den;
+  u128 tA = 0, tB = 1;                       /* tau_max = tA / tB */
+  int32_t i = 0, alive = n, ntrim = 0;
+  int32_t bi = -1;
+  int64_t bf = 0, bs = 1;
+  int64_t f = opt_weights(n, m, src, dst, c, a, peel_round, w);
+  sizes[0] = alive;
+  fs[0] = f;
+  for (;;) {
+    /* S_i is final here: candidate for the densest set */
+    if (alive > 0 && (bi < 0 || (u128)f * (u128)bs > (u128)bf * (u128)alive)) {
+      bi = i;
+      bf = f;
+      bs = alive;
+    }
+    if (alive == 0) break;
+    if (i + 1 >= cap) { free(w); return -2; }
+    i++;
+    /* S = S_{i-1}, weights w = w(S_{i-1}) */
+    const u128 s = (u128)(uint64_t)alive;
+    if (mode >= 1) {                         /* tau_max = max(tau_max, g / (k (1 + eps))) */
+      const u128 nA = (u128)(uint64_t)f * den, nB = s * K1;
+      if (nA * tB > tA * nB) { tA = nA; tB = nB; }
+    }
+    int32_t removed = 0;
+    for (int32_t u = 0; u < n; u++) {
+      if (peel_round[u] != PEEL_ALIVE) continue;
+      const u128 wu = (u128)(uint64_t)w[u];
+      const int le_tau = wu * tB <= tA;                                   /* w <= tau_max */
+      const int le_g = wu * s * den <= K1 * (u128)(uint64_t)f;           /* w <= k (1 + eps) g */
+      if (le_tau || le_g) { peel_round[u] = i; removed++; }
+    }
+    alive -= removed;
+    if (removed == 0) { free(w); return -1; }   /* cannot happen for eps >= 0 */
+    f = opt_weights(n, m, src, dst, c, a, peel_round, w);
+    if (mode == 2) {
+      for (;;) {
+        const u128 s2 = (u128)(uint64_t)alive;
+        int any = 0;                           /* some u with w_u < g(S) */
+        for (int32_t u = 0; u < n && !any; u++)
+          if (peel_round[u] == PEEL_ALIVE && (u128)(uint64_t)w[u] * s2 < (u128)(uint64_t)f) any = 1;
+        if (!any) break;
+        int32_t cut = 0;
+        for (int32_t u = 0; u < n; u++) {      /* w_u(S) < max(tau_max, g(S)), from w of this S */
+          if (peel_round[u] != PEEL_ALIVE) continue;
+          const u128 wu = (u128)(uint64_t)w[u];
+          if (wu * tB < tA || wu * s2 < (u128)(uint64_t)f) { peel_round[u] = i; cut++; }
+        }
+        alive -= cut;
+        ntrim++;
+        f = opt_weights(n, m, src, dst, c, a, peel_round, w);
+      }
+    }
+    sizes[i] = alive;
+    fs[i] = f;
+  }
+  *rounds = i;
+  *best = bi < 0 ? 0 : bi;
+  *trims = ntrim;
+  free(w);
   return 0;
 }
