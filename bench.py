@@ -200,7 +200,8 @@ def peel_bytes(metric: str, n: int, sizes, summary) -> dict:
     vertex): 20 B per alive vertex; update reads the neighbour id, its peel
     round and the edge weight (not for DG) and adds to w: 24 (DG) or 32 B
     per incidence; reduce reads list entry, w and a (FD): 12 or 20 B per
-    survivor."""
+    survivor. Counted per peeling round (a trimming step of local trimming
+    rereads the alive list and is not in it)."""
     alive_before = int(sum(sizes[:-1]))
     survivors = int(sum(sizes[1:])) + int(sizes[0])
     inc = int(summary["incidences"])
@@ -221,7 +222,8 @@ def copy_probe(mb: int):
 
 
 def peel_bench(args):
-    """Parallel peeling on a peeling input: every metric timed over full runs."""
+    """Parallel peeling on a peeling input: every metric and mode timed over
+    full runs; value and roofline come from the first metric and mode."""
     import torch
     import paper_2504_09311_amd as K
     from synth import workloads as W
@@ -235,43 +237,55 @@ def peel_bench(args):
     roof = None
     metrics = [x for x in args.peel_metrics.split(",") if x]
     assert metrics and set(metrics) <= {"DG", "DW", "FD"}, args.peel_metrics
+    modes = [x for x in args.peel_modes.split(",") if x]
+    assert modes and set(modes) <= {"plain", "gpo", "lpo"}, args.peel_modes
     for metric in metrics:
         t0 = time.perf_counter()
         G = K.PeelGraph(n, src, dst, metric, edge_w=inp["edge_w"], vertex_w=inp["vertex_w"])
         load_s = time.perf_counter() - t0
-        # the peel rounds stay in HBM in the timed runs (inputs and outputs
-        # resident); one more run returns them to host memory
-        for _ in range(max(1, args.warmup)):
-            G.peel(2, 1, 10, rounds=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, sizes, fs, sm = G.peel(2, 1, 10, rounds=False)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / args.steps
-        t0 = time.perf_counter()
-        G.peel(2, 1, 10)
-        wall_host = time.perf_counter() - t0
-        # one profiled run for the per-kernel times (events serialise it)
-        _, sizes_p, _, smp = G.peel(2, 1, 10, profile=True, rounds=False)
-        G.close()
-        bytes_ = peel_bytes(metric, n, sizes_p, smp)
-        kern = {k: dict(launches=int(smp[k + "_launches"]), total_ms=round(smp[k + "_ms"], 4),
-                        avg_us=round(smp[k + "_ms"] * 1e3 / max(1, smp[k + "_launches"]), 3)) for k in bytes_}
-        per[metric] = dict(seconds=round(wall, 5), edges_per_s=round(m / wall, 1),
-                           seconds_host_output=round(wall_host, 5), rounds=int(sm["rounds"]),
-                           best=int(sm["best"]), best_size=int(sm["best_size"]), best_f=int(sm["best_f"]),
-                           load_s=round(load_s, 3), kernels=kern)
-        if metric == metrics[0]:
+        per_mode = {}
+        for mode in modes:
+            lead = metric == metrics[0] and mode == modes[0]
+            # the peel rounds stay in HBM in the timed runs (inputs and outputs
+            # resident); one more run returns them to host memory
+            for _ in range(max(1, args.warmup)):
+                G.peel(2, 1, 10, rounds=False, mode=mode)
+            # per-class times from one untimed run with events on every class
+            _, sizes_p, _, smp = G.peel(2, 1, 10, profile=True, rounds=False, mode=mode)
+            bytes_ = peel_bytes(metric, n, sizes_p, smp)
+            kern = {k: dict(launches=int(smp[k + "_launches"]), total_ms=round(smp[k + "_ms"], 4),
+                            avg_us=round(smp[k + "_ms"] * 1e3 / max(1, smp[k + "_launches"]), 3)) for k in bytes_}
             dom = max(kern, key=lambda k: kern[k]["total_ms"])
-            launches = kern[dom]["launches"]
-            per_launch = bytes_[dom] / launches
-            avg_s = kern[dom]["total_ms"] / 1e3 / launches
-            roof = dict(kernel=dom, bound="hbm", achieved=round(per_launch / avg_s / 1e9, 2), peak=HBM_PEAK_GBS,
-                        unit="GB/s", frac=round(per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-                        traffic=measured_traffic("peel_" + dom, args.workload),
-                        bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 3), launches=launches)
-        log(metric, per[metric])
+            # timed runs; for the lead configuration the dominant class is
+            # bracketed by events (read after each run) for the roofline
+            dom_ms, dom_launches = 0.0, 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, sizes, fs, sm = G.peel(2, 1, 10, rounds=False, mode=mode, profile=[dom] if lead else False)
+                if lead:
+                    dom_ms += sm[dom + "_ms"]
+                    dom_launches += int(sm[dom + "_launches"])
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            t0 = time.perf_counter()
+            G.peel(2, 1, 10, mode=mode)
+            wall_host = time.perf_counter() - t0
+            per_mode[mode] = dict(seconds=round(wall, 5), edges_per_s=round(m / wall, 1),
+                                  seconds_host_output=round(wall_host, 5), rounds=int(sm["rounds"]),
+                                  trims=int(sm["trims"]), best=int(sm["best"]), best_size=int(sm["best_size"]),
+                                  best_f=int(sm["best_f"]), kernels=kern)
+            if lead and dom_launches:
+                per_launch = bytes_[dom] / max(1, kern[dom]["launches"])
+                avg_s = dom_ms / 1e3 / dom_launches
+                roof = dict(kernel=dom, bound="hbm", achieved=round(per_launch / avg_s / 1e9, 2), peak=HBM_PEAK_GBS,
+                            unit="GB/s", frac=round(per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                            traffic=measured_traffic("peel_" + dom, args.workload),
+                            bytes_per_launch=int(per_launch), avg_launch_us=round(avg_s * 1e6, 3),
+                            launches=dom_launches)
+            log(metric, mode, per_mode[mode])
+        G.close()
+        per[metric] = dict(load_s=round(load_s, 3), **per_mode)
     if args.copy_probe_mb:
         copy_probe(args.copy_probe_mb)
     cpu = None
@@ -289,11 +303,12 @@ def peel_bench(args):
                           f"edges), one full run in {dt:.1f} s")
     lead = metrics[0]
     out = {
-        "metric": PEEL_METRIC, "value": per[lead]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per[lead]["seconds"] * 1e3, 4),
+        "metric": PEEL_METRIC, "value": per[lead][modes[0]]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(per[lead][modes[0]]["seconds"] * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": dict(workload=args.workload, n=n, m=m, eps="1/10", k=2,
-                       metric=lead + (" (%s alongside)" % ", ".join(metrics[1:]) if metrics[1:] else "")),
+                       metric=lead + (" (%s alongside)" % ", ".join(metrics[1:]) if metrics[1:] else ""),
+                       mode=modes[0] + (" (%s alongside)" % ", ".join(modes[1:]) if modes[1:] else "")),
         "per_metric": per, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -319,6 +334,9 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0, help="also run a plain copy of this size")
     ap.add_argument("--peel-metrics", default="DG,DW,FD",
                     help="peeling inputs: metrics to run (the first gives value and roofline)")
+    ap.add_argument("--peel-modes", default="plain,gpo,lpo",
+                    help="peeling inputs: Algorithm 2 (plain), with the global threshold (gpo) and with local "
+                         "trimming (lpo); the first gives value and roofline")
     ap.add_argument("--serve", action="store_true", help="measure the serving loop instead of batches")
     ap.add_argument("--serve-sat", type=int, default=1024, help="queries for the saturation run")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each Poisson run")

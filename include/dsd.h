@@ -14,6 +14,15 @@
  *   w_u(S_{i-1}) <= k (1 + eps) g(S_{i-1}), until nothing is left; the
  *   answer is the first S_i of largest g.
  *
+ * The long-tail optimisations of Section 5 (kws_dsd_params.mode):
+ *   KWS_DSD_GPO (Algorithm 3): a global threshold tau_max, 0 at first and
+ *     raised at the start of every round to g(S_{i-1}) / (k (1 + eps)) when
+ *     that is larger; round i removes w_u <= max(tau_max, k (1 + eps) g).
+ *   KWS_DSD_LPO (Algorithm 4): as GPO, then, while some u in S_i has
+ *     w_u(S_i) < g(S_i), every u with w_u(S_i) < max(tau_max, g(S_i)) is
+ *     trimmed from S_i; S_i after its trimming is the round's set (and the
+ *     candidate for the densest).
+ *
  * Metrics (Section 2.1 and the example listing of Section 3):
  *   KWS_DSD_DG  a = 0, c = 1 (edge density)
  *   KWS_DSD_DW  a = 0, c = the given edge weight
@@ -65,13 +74,17 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out);
 void kws_dsd_free(kws_dsd_graph *g);
 
 /* k: 2 for the three metrics (the factor of Theorem 4.2); eps_num in
- * 0..1000, eps_den in 1..1000; profile = 1 times every kernel with HIP
- * events (the summary's *_ms and launches fields). */
+ * 0..1000, eps_den in 1..1000; profile = 1 brackets the kernel classes of
+ * profile_classes with HIP events (the summary's *_ms and launches fields;
+ * the events are read once the run has finished); mode: see above. */
+enum { KWS_DSD_PLAIN = 0, KWS_DSD_GPO = 1, KWS_DSD_LPO = 2 };
 typedef struct {
   int32_t k;
   int32_t eps_num;
   int32_t eps_den;
   int32_t profile;
+  int32_t mode;          /* KWS_DSD_PLAIN (Algorithm 2), KWS_DSD_GPO or KWS_DSD_LPO */
+  int32_t profile_classes;   /* with profile: bit 0 decide, 1 update, 2 reduce; 0 = all */
 } kws_dsd_params;
 
 typedef struct {
@@ -82,11 +95,14 @@ typedef struct {
   int64_t incidences;    /* edge endpoints processed by the neighbour updates */
   double decide_ms, update_ms, reduce_ms;   /* summed kernel time (profile = 1) */
   int64_t decide_launches, update_launches, reduce_launches;
+  int64_t trims;         /* trimming steps (LPO) */
+  int64_t steps;         /* rounds + trimming steps */
 } kws_dsd_summary;
 
 /* Runs the peeling on the graph's device copy. Outputs (host memory, each
  * may be NULL):
- *   peel_round[n]           the round (1..R) in which each vertex was peeled;
+ *   peel_round[n]           the round (1..R) in which each vertex was peeled
+ *                           or trimmed;
  *                           S_best = { v : peel_round[v] > best }. With NULL
  *                           the rounds stay in device memory only (see
  *                           kws_dsd_rounds)

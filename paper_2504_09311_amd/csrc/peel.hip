@@ -4,7 +4,8 @@
 // Layout: every edge is stored twice in an incidence CSR (once in the row
 // of each endpoint) with its weight; per vertex the current peeling weight
 // w (int64), the round it was peeled in, and two ping-pong lists of the
-// vertices still alive. A round is four launches, all on the device:
+// vertices still alive. A step is four launches (plus one thread that picks
+// its kind), all on the device:
 //   decide  scan the alive list: w_u * |S| * den <= k * (den + num) * f
 //           (128-bit products) puts u on the peeled list, else on the next
 //           alive list; appends are aggregated per wavefront;
@@ -36,16 +37,26 @@ constexpr int32_t ALIVE = KWS_DSD_ALIVE;
 constexpr int SMALL_DEG = 64;   // rows above this are summed by a wavefront at start
 constexpr int SMALL_PUSH = 16;  // peeled rows up to this are pushed by one thread
 
+// Kinds of step: a peeling step opens a round (Algorithm 2's test, or the
+// thresholds of Algorithms 3 and 4); a trimming step (Algorithm 4) removes
+// the vertices lighter than max(tau_max, g(S)) inside the round; after the
+// set is empty every step does nothing.
+enum { STEP_PEEL = 0, STEP_TRIM = 1, STEP_DONE = 2 };
+enum { MODE_PLAIN = 0, MODE_GPO = 1, MODE_LPO = 2 };
+
 struct PeelScalars {
   unsigned long long cnt[2];   // lengths of the two alive lists
-  unsigned long long nu;       // vertices peeled in the current round with small rows
+  unsigned long long nu;       // vertices removed by the current step with small rows
   unsigned long long nu_big;   // ... with rows above SMALL_PUSH incidences (listed from the end)
   unsigned long long sum2;     // sum of a + w over the survivors
-  unsigned long long deg_peel; // incidences of the vertices peeled in the current round
+  unsigned long long deg_peel; // incidences of the vertices removed by the current step
   unsigned long long deg_keep; // incidences of the survivors
-  long long f, s;              // f(S_i), |S_i| of the last finished round
+  unsigned long long nlt;      // survivors with w_u < g(S) (trimming test)
+  unsigned long long trims;    // trimming steps so far
+  unsigned long long tau_lo, tau_hi, tau_den;   // tau_max = (tau_hi:tau_lo) / tau_den
+  long long f, s;              // f(S), |S| of the current set
   long long best_f, best_s;
-  int best_i, pad;
+  int best_i, round, phase, pad;
 };
 
 __global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
@@ -110,11 +121,72 @@ __global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->cnt[0] = (unsigned long long)n;
     sc->cnt[1] = 0;
-    sc->nu = sc->nu_big = sc->sum2 = sc->deg_peel = sc->deg_keep = 0;
+    sc->nu = sc->nu_big = sc->sum2 = sc->deg_peel = sc->deg_keep = sc->nlt = sc->trims = 0;
+    sc->tau_lo = sc->tau_hi = 0;
+    sc->tau_den = 1;
     sc->f = sc->s = sc->best_f = 0;
     sc->best_i = -1;
     sc->best_s = 1;
+    sc->round = 0;
+    sc->phase = STEP_PEEL;
   }
+}
+
+__device__ __forceinline__ u128 tau_num(const PeelScalars *sc) {
+  return ((u128)sc->tau_hi << 64) | (u128)sc->tau_lo;
+}
+
+// LPO: the survivors lighter than g(S) (w_u |S| < f(S)), one atomic per block
+__global__ __launch_bounds__(BLOCK) void k_count_lt(const int32_t *__restrict__ la, int ca, PeelScalars *sc,
+                                                    const int64_t *__restrict__ w) {
+  __shared__ unsigned long long s_n;
+  if (sc->round == 0) return;          // no trimming before the first peeling step
+  const unsigned long long count = sc->cnt[ca];
+  const u128 f = (u128)(uint64_t)sc->f, sz = (u128)(uint64_t)sc->s;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  unsigned long long c = 0;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < count;
+       i += (unsigned long long)gridDim.x * BLOCK)
+    if ((u128)(uint64_t)w[la[i]] * sz < f) c++;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(&s_n, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_n) atomicAdd(&sc->nlt, s_n);
+}
+
+// one thread: the kind of the next step. A trimming step while (LPO) some
+// survivor of the round is lighter than g(S); otherwise the round is over:
+// its set is a candidate for the densest, and the next round starts with
+// tau_max refined (GPO, LPO) from g of that set.
+__global__ void k_phase(PeelScalars *sc, int32_t mode, int32_t k, int32_t num, int32_t den) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const long long f = sc->f, s = sc->s;
+  if (s == 0) { sc->phase = STEP_DONE; return; }
+  if (mode == MODE_LPO && sc->round > 0 && sc->nlt > 0) {
+    sc->phase = STEP_TRIM;
+    sc->trims++;
+    sc->nlt = 0;
+    return;
+  }
+  sc->nlt = 0;
+  if (sc->best_i < 0 || (u128)(uint64_t)f * (u128)(uint64_t)sc->best_s >
+                            (u128)(uint64_t)sc->best_f * (u128)(uint64_t)s) {
+    sc->best_i = sc->round;
+    sc->best_f = f;
+    sc->best_s = s;
+  }
+  if (mode != MODE_PLAIN) {            // tau_max = max(tau_max, g / (k (1 + eps)))
+    const u128 nA = (u128)(uint64_t)f * (u128)(uint64_t)den;
+    const u128 nB = (u128)(uint64_t)s * (u128)(uint64_t)k * (u128)(uint64_t)(den + num);
+    if (nA * (u128)sc->tau_den > tau_num(sc) * nB) {
+      sc->tau_lo = (unsigned long long)nA;
+      sc->tau_hi = (unsigned long long)(nA >> 64);
+      sc->tau_den = (unsigned long long)nB;
+    }
+  }
+  sc->round++;
+  sc->phase = STEP_PEEL;
 }
 
 // exclusive prefix sum over the block of one value per thread
@@ -143,16 +215,24 @@ __device__ __forceinline__ unsigned block_excl_scan(unsigned x, unsigned *s_w, u
 // of both sets choose how the weights are updated
 constexpr int PER = 16, CHUNK = PER * BLOCK;
 
-__global__ __launch_bounds__(BLOCK) void k_decide(int32_t round, const int32_t *__restrict__ la, int ca,
+__global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la, int ca,
                                                   int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
                                                   int32_t n_total, PeelScalars *sc, const int64_t *__restrict__ w,
                                                   const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd,
                                                   int32_t k, int32_t num, int32_t den) {
   __shared__ unsigned s_w[BLOCK / 64];
   __shared__ unsigned long long s_base[3];
+  const int phase = sc->phase;
+  if (phase == STEP_DONE) return;
+  const int32_t round = sc->round;
   const unsigned long long count = sc->cnt[ca];
-  const u128 rhs = (u128)(uint64_t)k * (u128)(uint64_t)(den + num) * (u128)(uint64_t)sc->f;
-  const u128 scale = (u128)(uint64_t)sc->s * (u128)(uint64_t)den;
+  // peeling: w <= max(tau_max, k (1 + eps) g), i.e. w tau_den <= tau or
+  // w |S| den <= k (den + num) f; trimming: w < max(tau_max, g), i.e.
+  // w tau_den < tau or w |S| < f
+  const bool trim = phase == STEP_TRIM;
+  const u128 rhs = trim ? (u128)(uint64_t)sc->f : (u128)(uint64_t)k * (u128)(uint64_t)(den + num) * (u128)(uint64_t)sc->f;
+  const u128 scale = trim ? (u128)(uint64_t)sc->s : (u128)(uint64_t)sc->s * (u128)(uint64_t)den;
+  const u128 tau = tau_num(sc), tden = (u128)sc->tau_den;
   for (unsigned long long c0 = (unsigned long long)blockIdx.x * CHUNK; c0 < count;
        c0 += (unsigned long long)gridDim.x * CHUNK) {
     int32_t v[PER];
@@ -167,7 +247,9 @@ __global__ __launch_bounds__(BLOCK) void k_decide(int32_t round, const int32_t *
     for (int j = 0; j < PER; j++) {
       if (v[j] < 0) continue;
       const unsigned long long d = (unsigned long long)(ptr[v[j] + 1] - ptr[v[j]]);
-      if ((u128)(uint64_t)w[v[j]] * scale <= rhs) {
+      const u128 wv = (u128)(uint64_t)w[v[j]];
+      const bool out = trim ? (wv * tden < tau || wv * scale < rhs) : (wv * tden <= tau || wv * scale <= rhs);
+      if (out) {
         peel_bits |= 1u << j;
         if (d > SMALL_PUSH) { big_bits |= 1u << j; nb++; } else np++;
         dp += d;
@@ -306,17 +388,15 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ li
   }
 }
 
-// close round `round`: survivors are in list cl; the next round fills 1 - cl
-__global__ void k_end(int32_t round, int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int32_t cap) {
+// close a step: survivors are in list cl; the next step fills 1 - cl. The
+// record of the round is rewritten by every step of it (the last, after
+// trimming, stays).
+__global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int32_t cap) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (sc->phase == STEP_DONE) return;
+  const int32_t round = sc->round;
   const long long f = (long long)(sc->sum2 / 2ull), s = (long long)sc->cnt[cl];
   if (round < cap) { sizes[round] = s; fs[round] = f; }
-  if (s > 0 && (sc->best_i < 0 || (u128)(uint64_t)f * (u128)(uint64_t)sc->best_s >
-                                      (u128)(uint64_t)sc->best_f * (u128)(uint64_t)s)) {
-    sc->best_i = round;
-    sc->best_f = f;
-    sc->best_s = s;
-  }
   sc->f = f;
   sc->s = s;
   sc->sum2 = 0;
@@ -374,24 +454,42 @@ kws_status dev_array(T **p, size_t count, const char *what) {
 }
 
 // event timing of one kernel class
+// event pairs of the timed kernel classes of one run, read after its last
+// synchronisation (no wait while steps are enqueued)
+enum { DSD_DECIDE = 0, DSD_UPDATE = 1, DSD_REDUCE = 2 };
+struct DsdEvents {
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  ~DsdEvents() {
+    for (Rec &r : recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+  }
+  void collect(kws_dsd_summary &sum) {
+    double *ms[3] = {&sum.decide_ms, &sum.update_ms, &sum.reduce_ms};
+    int64_t *n[3] = {&sum.decide_launches, &sum.update_launches, &sum.reduce_launches};
+    for (Rec &r : recs) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) { *ms[r.cls] += t; (*n[r.cls])++; }
+    }
+  }
+};
+
 struct DsdTimer {
-  bool on;
+  DsdEvents *log;
+  int cls;
   hipStream_t s;
-  double *ms;
-  int64_t *launches;
-  hipEvent_t a = nullptr, b = nullptr;
-  DsdTimer(bool on_, hipStream_t s_, double *ms_, int64_t *l_) : on(on_), s(s_), ms(ms_), launches(l_) {
-    if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) hipEventRecord(a, s);
-    else on = false;
+  hipEvent_t a = nullptr;
+  DsdTimer(bool on, int cls_, hipStream_t s_, DsdEvents *log_) : log(nullptr), cls(cls_), s(s_) {
+    if (on && hipEventCreate(&a) == hipSuccess) {
+      log = log_;
+      hipEventRecord(a, s);
+    }
   }
   ~DsdTimer() {
-    if (!on) return;
+    if (!log) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return; }
     hipEventRecord(b, s);
-    hipEventSynchronize(b);
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, a, b) == hipSuccess) { *ms += t; (*launches)++; }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    log->recs.push_back({cls, a, b});
   }
 };
 
@@ -519,6 +617,8 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   if (!g || !p) return fail(KWS_EINVAL, "null argument");
   if (p->k < 1 || p->k > 64 || p->eps_num < 0 || p->eps_num > 1000 || p->eps_den < 1 || p->eps_den > 1000)
     return fail(KWS_EINVAL, "k must be 1..64, eps_num 0..1000, eps_den 1..1000");
+  if (p->mode < KWS_DSD_PLAIN || p->mode > KWS_DSD_LPO) return fail(KWS_EINVAL, "unknown peeling mode %d", p->mode);
+  if (p->profile_classes < 0 || p->profile_classes > 7) return fail(KWS_EINVAL, "profile_classes must be 0..7");
   if ((sizes || f) && cap < 1) return fail(KWS_EINVAL, "cap must be >= 1 with sizes or f");
 
   hipStream_t s = g->stream;
@@ -536,32 +636,42 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     g->d_cap = want_cap;
   }
   kws_dsd_summary sum{};
-  const bool prof = p->profile != 0;
+  // profile 0: no events; otherwise events around the classes of
+  // profile_classes (bit 0 decide, 1 update, 2 reduce; 0 = every class)
+  const int pmask = p->profile ? (p->profile_classes ? p->profile_classes : 7) : 0;
+  const bool t_dec = pmask & 1, t_upd = (pmask >> 1) & 1, t_red = (pmask >> 2) & 1;
+  DsdEvents evlog;
   const int64_t resident = 2048;
   KWS_HIP(hipGetLastError());
   g->has_run = false;
   k_scalars_init<<<1, 64, 0, s>>>(g->sc, n);
   k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd, g->list[0]);
   {
-    DsdTimer t(prof, s, &sum.reduce_ms, &sum.reduce_launches);
+    DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
     k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
   }
-  k_end<<<1, 64, 0, s>>>(0, 0, g->sc, g->d_sizes, g->d_f, g->d_cap);
+  k_end<<<1, 64, 0, s>>>(0, g->sc, g->d_sizes, g->d_f, g->d_cap);
   KWS_HIP(hipGetLastError());
-  int64_t known = n;   // an upper bound of |S| (read back every few rounds)
-  int32_t round = 0;
+  // Steps are enqueued without waiting: the device decides whether a step
+  // peels (a new round), trims (LPO) or, once the set is empty, does
+  // nothing. Every real step removes a vertex, so there are at most n.
+  int64_t known = n;   // an upper bound of |S| (read back every few steps)
+  int64_t step = 0;
   while (known > 0) {
-    if (round + 1 >= g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
-    round++;
-    const int ca = (round - 1) & 1, cb = round & 1;
+    if (step > (int64_t)n + 1) return fail(KWS_EDEVICE, "peeling did not finish in %d steps", n + 1);
+    step++;
+    const int ca = (int)((step - 1) & 1), cb = (int)(step & 1);
     {
-      DsdTimer t(prof, s, &sum.decide_ms, &sum.decide_launches);
-      k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(round, g->list[ca], ca, g->list[cb], cb, g->ul,
-                                                                   n, g->sc, g->w, g->ptr, g->rnd, p->k, p->eps_num,
+      DsdTimer t(t_dec, DSD_DECIDE, s, &evlog);
+      if (p->mode == KWS_DSD_LPO)
+        k_count_lt<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->sc, g->w);
+      k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
+      k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
+                                                                   g->w, g->ptr, g->rnd, p->k, p->eps_num,
                                                                    p->eps_den);
     }
     {
-      DsdTimer t(prof, s, &sum.update_ms, &sum.update_launches);
+      DsdTimer t(t_upd, DSD_UPDATE, s, &evlog);
       k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, g->ptr, g->nbr, g->wt,
                                                                             g->rnd, g->w);
       k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
@@ -569,30 +679,32 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
                                                          g->w);
     }
     {
-      DsdTimer t(prof, s, &sum.reduce_ms, &sum.reduce_launches);
+      DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
       k_reduce<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
     }
-    k_end<<<1, 64, 0, s>>>(round, cb, g->sc, g->d_sizes, g->d_f, g->d_cap);
+    k_end<<<1, 64, 0, s>>>(cb, g->sc, g->d_sizes, g->d_f, g->d_cap);
     KWS_HIP(hipGetLastError());
-    if (round % 4 == 0 || known < 4096) {
+    if (step % 4 == 0 || known < 4096) {
       PeelScalars h;
       KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
       KWS_HIP(hipStreamSynchronize(s));
       known = h.s;
+      if (h.round + 1 >= g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
     }
   }
   PeelScalars h;
   KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
   KWS_HIP(hipStreamSynchronize(s));
-  // R is the first round that left nothing; rounds enqueued past it did nothing
+  // the last round is the one that left nothing (steps enqueued after it did nothing)
+  const int32_t round = h.round;
+  if (round + 1 > g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
   std::vector<int64_t> hs((size_t)round + 1), hf((size_t)round + 1);
   KWS_HIP(hipMemcpyAsync(hs.data(), g->d_sizes, sizeof(int64_t) * hs.size(), hipMemcpyDeviceToHost, s));
   KWS_HIP(hipMemcpyAsync(hf.data(), g->d_f, sizeof(int64_t) * hf.size(), hipMemcpyDeviceToHost, s));
   if (peel_round && n > 0)
     KWS_HIP(hipMemcpyAsync(peel_round, g->rnd, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
   KWS_HIP(hipStreamSynchronize(s));
-  int32_t R = 0;
-  while (R < round && hs[R] > 0) R++;
+  const int32_t R = round;
   if ((sizes || f) && R + 1 > cap) return fail(KWS_EOVERFLOW, "%d rounds do not fit cap %d", R, cap);
   if (sizes) std::memcpy(sizes, hs.data(), sizeof(int64_t) * ((size_t)R + 1));
   if (f) std::memcpy(f, hf.data(), sizeof(int64_t) * ((size_t)R + 1));
@@ -600,7 +712,10 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   sum.best = h.best_i < 0 ? 0 : h.best_i;
   sum.best_size = h.best_i < 0 ? 0 : h.best_s;
   sum.best_f = h.best_i < 0 ? 0 : h.best_f;
-  sum.incidences = 2 * g->m;   // every vertex is peeled once: each edge is visited from both ends
+  sum.incidences = 2 * g->m;   // every vertex is removed once: each edge is visited from both ends
+  sum.trims = (int64_t)h.trims;
+  evlog.collect(sum);
+  sum.steps = (int64_t)R + (int64_t)h.trims;
   if (summary) *summary = sum;
   g->has_run = true;
   return KWS_OK;

@@ -69,14 +69,15 @@ class DsdDesc(C.Structure):
 
 
 class DsdParams(C.Structure):
-    _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32), ("profile", C.c_int32)]
+    _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32), ("profile", C.c_int32),
+                ("mode", C.c_int32), ("profile_classes", C.c_int32)]
 
 
 class DsdSummary(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("best", C.c_int32), ("best_size", C.c_int64), ("best_f", C.c_int64),
                 ("incidences", C.c_int64), ("decide_ms", C.c_double), ("update_ms", C.c_double),
                 ("reduce_ms", C.c_double), ("decide_launches", C.c_int64), ("update_launches", C.c_int64),
-                ("reduce_launches", C.c_int64)]
+                ("reduce_launches", C.c_int64), ("trims", C.c_int64), ("steps", C.c_int64)]
 
 
 class TuneReport(C.Structure):
@@ -520,10 +521,17 @@ class PeelGraph:
         _check(lib.kws_dsd_load(C.byref(d), C.byref(h)))
         self.h = h
 
-    def peel(self, k: int = 2, eps_num: int = 1, eps_den: int = 10, profile: bool = False, cap: int = 0,
-             rounds: bool = True):
+    MODES = {"plain": 0, "gpo": 1, "lpo": 2}
+
+    PROFILE_CLASSES = {"decide": 1, "update": 2, "reduce": 4}
+
+    def peel(self, k: int = 2, eps_num: int = 1, eps_den: int = 10, profile=False, cap: int = 0,
+             rounds: bool = True, mode: str = "plain"):
         """(peel_round[n], sizes[R+1], f[R+1], summary dict) of one run.
 
+        mode: "plain" (Algorithm 2), "gpo" (global threshold, Algorithm 3)
+        or "lpo" (and local trimming, Algorithm 4). profile: True times every
+        kernel class with events, a list of class names times only those.
         rounds=False leaves the peel rounds in device memory (None is
         returned in their place; ``rounds()`` fetches them later)."""
         cap = cap or 65536
@@ -531,7 +539,11 @@ class PeelGraph:
         fs = np.empty(cap, np.int64)
         sm = DsdSummary()
         pr = np.empty(max(self.n, 1), np.int32) if rounds else None
-        p = DsdParams(k, eps_num, eps_den, 1 if profile else 0)
+        pmask = 0
+        if profile and not isinstance(profile, bool):
+            for nm in profile:
+                pmask |= self.PROFILE_CLASSES[nm]
+        p = DsdParams(k, eps_num, eps_den, 1 if profile else 0, self.MODES[mode], pmask)
         _check(self._lib.kws_dsd_peel(self.h, C.byref(p), pr.ctypes.data if rounds else None, sizes.ctypes.data,
                                       fs.ctypes.data, cap, C.byref(sm)))
         R = int(sm.rounds)

@@ -138,3 +138,63 @@ def test_rounds_left_on_device(K):
         assert np.array_equal(sizes_d, sizes) and np.array_equal(fs_d, fs) and sm_d["best"] == sm["best"], metric
         assert G.device_rounds() != 0
         G.close()
+
+
+# ---- the long-tail optimisations (global threshold, local trimming)
+
+def check_same_opt(K, n, src, dst, ew, vw, metric, num, den, mode, what, c=None, a=None):
+    if c is None:
+        c, a = oracle.metric_weights(metric, src, dst, n, ew, vw)
+    want = oracle.peel_opt(n, src, dst, c, a, 2, num, den, mode=mode)
+    G = K.PeelGraph(n, src, dst, metric, edge_w=ew, vertex_w=vw)
+    pr, sizes, fs, sm = G.peel(2, num, den, mode=mode)
+    G.close()
+    assert np.array_equal(pr, want.peel_round), what
+    assert np.array_equal(sizes, want.sizes) and np.array_equal(fs, want.f), what
+    assert sm["rounds"] == want.rounds and sm["best"] == want.best and sm["trims"] == want.trims, what
+    assert sm["steps"] == want.rounds + want.trims, what
+
+
+@pytest.mark.parametrize("mode", ["gpo", "lpo"])
+def test_optimised_tiny_random(K, mode):
+    for seed in range(200, 320):
+        n, src, dst, ew, vw = random_graph(seed, n_max=24, p_max=0.4)
+        for metric in oracle.METRICS:
+            num, den = [(0, 1), (1, 10), (1, 2), (3, 1)][seed % 4]
+            check_same_opt(K, n, src, dst, ew, vw, metric, num, den, mode, f"tiny {seed} {metric} {num}/{den} {mode}")
+
+
+def test_optimised_threshold_and_strict_trimming(K):
+    from test_peel_pins import powerlaw_graph
+    src, dst, ew, vw = powerlaw_graph(1495, 39)           # the global threshold changes the rounds here
+    for mode in ("gpo", "lpo"):
+        check_same_opt(K, 39, src, dst, ew, vw, "DW", 1, 10, mode, f"powerlaw 1495 {mode}")
+    # vertex weights only (FD with no edges): 22 zeros, then 1, 4, 7; two trims
+    e = np.zeros(0, np.int32)
+    vw = np.array([0] * 22 + [1, 4, 7], np.int64)
+    check_same_opt(K, 25, e, e, np.zeros(0, np.int64), vw, "FD", 0, 1, "lpo", "strict trimming")
+    G = K.PeelGraph(25, e, e, "FD", vertex_w=vw)
+    _, _, _, sm = G.peel(2, 0, 1, mode="lpo")
+    G.close()
+    assert sm["trims"] == 2
+
+
+@pytest.mark.parametrize("name,scale", [("peel_chunglu10k", None), ("peel_rmat20", 14), ("peel_rmat20", 16)])
+def test_optimised_synthetic_graphs(K, name, scale):
+    inp = workloads.peel_input(name, scale=scale)
+    for metric in oracle.METRICS:
+        for mode in ("gpo", "lpo"):
+            for num, den in [(1, 10), (1, 2)]:
+                say(name, scale, metric, mode, num, den)
+                check_same_opt(K, inp["n"], inp["src"], inp["dst"], inp["edge_w"], inp["vertex_w"], metric, num, den,
+                               mode, f"{name} {scale} {metric} {mode} {num}/{den}")
+
+
+def test_optimised_rmat24_full_scale(K):
+    inp = workloads.peel_input("peel_rmat24")
+    n = inp["n"]
+    c, a = oracle.metric_weights("DG", inp["src"], inp["dst"], n)
+    for mode in ("gpo", "lpo"):
+        say("peel rmat24", mode)
+        check_same_opt(K, n, inp["src"], inp["dst"], inp["edge_w"], inp["vertex_w"], "DG", 1, 10, mode,
+                       f"rmat24 DG {mode}", c=c, a=a)
