@@ -3,16 +3,20 @@
 //
 // Layout: every edge is stored twice in an incidence CSR (once in the row
 // of each endpoint) with its weight; per vertex the current peeling weight
-// w (int64), the round it was peeled in, and two ping-pong lists of the
-// vertices still alive. A step is four launches (plus one thread that picks
-// its kind), all on the device:
+// w (int64), the round it was peeled in and an alive bit (the bitmap is
+// n/8 bytes, so the random alive tests of the update hit L2), and two
+// ping-pong lists of the vertices still alive. A step is four launches
+// (plus one thread that picks its kind), all on the device:
 //   decide  scan the alive list: w_u * |S| * den <= k * (den + num) * f
 //           (128-bit products) puts u on the peeled list, else on the next
-//           alive list; appends are aggregated per wavefront;
+//           alive list (and its row, in pieces, on the pull list); appends
+//           are aggregated per block;
 //   update  push: the peeled vertices subtract their edge weights from the
 //           neighbours still alive (64-bit atomics); or pull: the survivors
-//           re-sum their alive neighbours (rows split over blocks), whichever
-//           set has fewer incidences (chosen on the device);
+//           re-sum their alive neighbours, a wavefront per row piece;
+//           push only while the peeled vertices have a small share of the
+//           incidences, as it pays an atomic per alive neighbour (chosen on
+//           the device);
 //   reduce  sum of a + w over the survivors (= 2 f(S_i));
 //   end     one thread: f, |S|, the per-round record and the densest S_i.
 // The host only enqueues rounds and reads |S| every few rounds to stop.
@@ -36,6 +40,11 @@ typedef unsigned __int128 u128;
 constexpr int32_t ALIVE = KWS_DSD_ALIVE;
 constexpr int SMALL_DEG = 64;   // rows above this are summed by a wavefront at start
 constexpr int SMALL_PUSH = 16;  // peeled rows up to this are pushed by one thread
+constexpr int PIECE = 1024;     // incidences of a survivor's row summed by one wavefront (pull)
+// push costs an atomic per alive neighbour, pull streams ids and tests a bit:
+// push is taken while the removed vertices have at most 1/PUSH_COST of the
+// survivors' incidences
+constexpr unsigned long long PUSH_COST = 4;
 
 // Kinds of step: a peeling step opens a round (Algorithm 2's test, or the
 // thresholds of Algorithms 3 and 4); a trimming step (Algorithm 4) removes
@@ -52,6 +61,7 @@ struct PeelScalars {
   unsigned long long deg_peel; // incidences of the vertices removed by the current step
   unsigned long long deg_keep; // incidences of the survivors
   unsigned long long nlt;      // survivors with w_u < g(S) (trimming test)
+  unsigned long long nitems;   // pull work items (row pieces of the survivors)
   unsigned long long trims;    // trimming steps so far
   unsigned long long tau_lo, tau_hi, tau_den;   // tau_max = (tau_hi:tau_lo) / tau_den
   long long f, s;              // f(S), |S| of the current set
@@ -95,11 +105,13 @@ __global__ __launch_bounds__(BLOCK) void k_w0_small(int32_t n, const int64_t *__
 
 // start of a run: S_0 = V
 __global__ __launch_bounds__(BLOCK) void k_start(int32_t n, const int64_t *__restrict__ w0, int64_t *__restrict__ w,
-                                                 int32_t *__restrict__ rnd, int32_t *__restrict__ list) {
+                                                 int32_t *__restrict__ rnd, int32_t *__restrict__ list,
+                                                 uint32_t *__restrict__ alive) {
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
     w[v] = w0[v];
     rnd[v] = ALIVE;
     list[v] = (int32_t)v;
+    if ((v & 31) == 0) alive[v >> 5] = n - v >= 32 ? ~0u : (1u << (n - v)) - 1u;
   }
 }
 
@@ -121,7 +133,7 @@ __global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->cnt[0] = (unsigned long long)n;
     sc->cnt[1] = 0;
-    sc->nu = sc->nu_big = sc->sum2 = sc->deg_peel = sc->deg_keep = sc->nlt = sc->trims = 0;
+    sc->nu = sc->nu_big = sc->sum2 = sc->deg_peel = sc->deg_keep = sc->nlt = sc->trims = sc->nitems = 0;
     sc->tau_lo = sc->tau_hi = 0;
     sc->tau_den = 1;
     sc->f = sc->s = sc->best_f = 0;
@@ -134,6 +146,32 @@ __global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
 
 __device__ __forceinline__ u128 tau_num(const PeelScalars *sc) {
   return ((u128)sc->tau_hi << 64) | (u128)sc->tau_lo;
+}
+
+__device__ __forceinline__ bool pull_step(const PeelScalars *sc) {
+  return sc->deg_peel * PUSH_COST > sc->deg_keep;
+}
+
+// one bit per vertex, set while it is alive (n/8 bytes: stays in L2)
+__device__ __forceinline__ bool is_alive(const uint32_t *__restrict__ alive, int32_t x) {
+  return (alive[x >> 5] >> (x & 31)) & 1u;
+}
+
+// clear the alive bits of the lanes that remove their vertex. Every lane of
+// the wavefront calls this (v < 0: no vertex); lanes with vertices of one
+// 32-bit word next to each other merge their bits first, so a run of
+// consecutive vertices costs one atomic per word.
+__device__ __forceinline__ void clear_alive(uint32_t *alive, int32_t v, bool out) {
+  const int lane = threadIdx.x & 63;
+  const int32_t word = v >= 0 ? (v >> 5) : -1 - lane;
+  uint32_t bits = out ? 1u << (v & 31) : 0u;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t w2 = __shfl_down(word, off);
+    const uint32_t b2 = __shfl_down(bits, off);
+    if (lane + off < 64 && w2 == word) bits |= b2;
+  }
+  const int32_t prev = __shfl_up(word, 1);
+  if (bits && (lane == 0 || prev != word)) atomicAnd(&alive[word], ~bits);
 }
 
 // LPO: the survivors lighter than g(S) (w_u |S| < f(S)), one atomic per block
@@ -212,16 +250,20 @@ __device__ __forceinline__ unsigned block_excl_scan(unsigned x, unsigned *s_w, u
 // decide: a block takes CHUNK alive vertices at a time (PER per thread,
 // strided so loads coalesce), tests each, and appends the peeled and the
 // surviving ones with one reservation per list and chunk; the degree sums
-// of both sets choose how the weights are updated
+// of both sets choose how the weights are updated. A removed vertex gets
+// its round and loses its alive bit; a survivor's row is listed in pieces
+// of PIECE incidences for the pull.
 constexpr int PER = 16, CHUNK = PER * BLOCK;
 
 __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la, int ca,
                                                   int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
                                                   int32_t n_total, PeelScalars *sc, const int64_t *__restrict__ w,
                                                   const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd,
+                                                  uint32_t *__restrict__ alive,
+                                                  unsigned long long *__restrict__ items,
                                                   int32_t k, int32_t num, int32_t den) {
   __shared__ unsigned s_w[BLOCK / 64];
-  __shared__ unsigned long long s_base[3];
+  __shared__ unsigned long long s_base[4];
   const int phase = sc->phase;
   if (phase == STEP_DONE) return;
   const int32_t round = sc->round;
@@ -236,7 +278,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
   for (unsigned long long c0 = (unsigned long long)blockIdx.x * CHUNK; c0 < count;
        c0 += (unsigned long long)gridDim.x * CHUNK) {
     int32_t v[PER];
-    unsigned peel_bits = 0, big_bits = 0, np = 0, nb = 0, nk = 0;
+    uint32_t pcs[PER];   // pieces of a survivor's row
+    unsigned peel_bits = 0, big_bits = 0, np = 0, nb = 0, nk = 0, ni = 0;
     unsigned long long dp = 0, dk = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
@@ -245,6 +288,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
     }
 #pragma unroll
     for (int j = 0; j < PER; j++) {
+      pcs[j] = 0;
       if (v[j] < 0) continue;
       const unsigned long long d = (unsigned long long)(ptr[v[j] + 1] - ptr[v[j]]);
       const u128 wv = (u128)(uint64_t)w[v[j]];
@@ -256,12 +300,15 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
       } else {
         nk++;
         dk += d;
+        pcs[j] = (uint32_t)((d + PIECE - 1) / PIECE);
+        ni += pcs[j];
       }
     }
-    unsigned tp, tb, tk;
+    unsigned tp, tb, tk, ti;
     const unsigned op = block_excl_scan(np, s_w, &tp);
     const unsigned ob = block_excl_scan(nb, s_w, &tb);
     const unsigned ok = block_excl_scan(nk, s_w, &tk);
+    const unsigned oi = block_excl_scan(ni, s_w, &ti);
     for (int off = 32; off > 0; off >>= 1) {
       dp += __shfl_xor(dp, off);
       dk += __shfl_xor(dk, off);
@@ -274,12 +321,14 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
       s_base[0] = tp ? atomicAdd(&sc->nu, (unsigned long long)tp) : 0ull;
       s_base[1] = tk ? atomicAdd(&sc->cnt[cb], (unsigned long long)tk) : 0ull;
       s_base[2] = tb ? atomicAdd(&sc->nu_big, (unsigned long long)tb) : 0ull;
+      s_base[3] = ti ? atomicAdd(&sc->nitems, (unsigned long long)ti) : 0ull;
     }
     __syncthreads();
-    unsigned long long pu = s_base[0] + op, pk = s_base[1] + ok, pb = s_base[2] + ob;
+    unsigned long long pu = s_base[0] + op, pk = s_base[1] + ok, pb = s_base[2] + ob, pi = s_base[3] + oi;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; j++) {
+      clear_alive(alive, v[j], (peel_bits >> j) & 1u);
       if (v[j] < 0) continue;
       if ((peel_bits >> j) & 1u) {
         rnd[v[j]] = round;
@@ -287,28 +336,29 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
         else ul[pu++] = v[j];
       } else {
         lb[pk++] = v[j];
+        for (uint32_t q = 0; q < pcs[j]; q++) items[pi++] = ((unsigned long long)v[j] << 32) | q;
       }
     }
   }
 }
 
-// push: the peeled vertices subtract their edge weights from the neighbours
-// still alive; a thread per vertex with a small row, a wavefront per vertex
-// with a large one. Runs when the peeled vertices have no more incidences
-// than the survivors.
+// push: the removed vertices subtract their edge weights from the
+// neighbours still alive; a thread per vertex with a small row, a
+// wavefront per vertex with a large one. Runs while the removed vertices
+// have few incidences next to the survivors' (pull_step).
 __global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict__ ul, int32_t n_total,
                                                        PeelScalars *sc, const int64_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ nbr,
                                                        const int64_t *__restrict__ wt,
-                                                       const int32_t *__restrict__ rnd, int64_t *__restrict__ w) {
-  if (sc->deg_peel > sc->deg_keep) return;
+                                                       const uint32_t *__restrict__ alive, int64_t *__restrict__ w) {
+  if (pull_step(sc)) return;
   const unsigned long long nu = sc->nu, nb = sc->nu_big;
   for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < nu;
        i += (unsigned long long)gridDim.x * BLOCK) {
     const int32_t u = ul[i];
     for (int64_t j = ptr[u]; j < ptr[u + 1]; j++) {
       const int32_t x = nbr[j];
-      if (rnd[x] == ALIVE) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
+      if (is_alive(alive, x)) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
     }
   }
   const int lane = threadIdx.x & 63;
@@ -318,53 +368,44 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict
     const int64_t b = ptr[u], e = ptr[u + 1];
     for (int64_t j = b + lane; j < e; j += 64) {
       const int32_t x = nbr[j];
-      if (rnd[x] == ALIVE) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
+      if (is_alive(alive, x)) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
     }
   }
 }
 
-// pull (when the survivors have fewer incidences than the peeled vertices):
-// the survivors' weights restart from a and every block adds the alive
-// neighbours of its part of one survivor's row; the blocks share the
-// survivors, several blocks per row when there are fewer survivors than
-// blocks, so a handful of high-degree survivors still fill the chip.
+// pull: the survivors' weights restart from a, and each piece of PIECE
+// incidences of a survivor's row (listed by decide) is summed over the
+// alive neighbours by one wavefront and added with one atomic, so hub rows
+// spread over many wavefronts.
 __global__ __launch_bounds__(BLOCK) void k_update_pull_reset(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
                                                              const int64_t *__restrict__ a, int64_t *__restrict__ w) {
-  if (sc->deg_peel <= sc->deg_keep) return;
+  if (!pull_step(sc)) return;
   const unsigned long long count = sc->cnt[cb];
   for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < count;
        i += (unsigned long long)gridDim.x * BLOCK)
     w[lb[i]] = a ? a[lb[i]] : 0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_update_pull(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+__global__ __launch_bounds__(BLOCK) void k_update_pull(const unsigned long long *__restrict__ items, PeelScalars *sc,
                                                        const int64_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ nbr,
                                                        const int64_t *__restrict__ wt,
-                                                       const int32_t *__restrict__ rnd, int64_t *__restrict__ w) {
-  __shared__ unsigned long long s_part[BLOCK / 64];
-  if (sc->deg_peel <= sc->deg_keep) return;
-  const unsigned long long count = sc->cnt[cb];
-  if (count == 0) return;
-  const unsigned long long bps = max(1ull, (unsigned long long)gridDim.x / count);   // blocks per row
-  for (unsigned long long it = blockIdx.x; it < count * bps; it += gridDim.x) {
-    const int32_t v = lb[it / bps];
-    const unsigned long long part = it % bps;
-    const int64_t b = ptr[v], len = ptr[v + 1] - b;
-    const int64_t lo = b + (int64_t)((unsigned long long)len * part / bps);
-    const int64_t hi = b + (int64_t)((unsigned long long)len * (part + 1) / bps);
+                                                       const uint32_t *__restrict__ alive, int64_t *__restrict__ w) {
+  if (!pull_step(sc)) return;
+  const unsigned long long count = sc->nitems;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long waves = ((unsigned long long)gridDim.x * BLOCK) >> 6;
+  for (unsigned long long it = ((unsigned long long)blockIdx.x * BLOCK + threadIdx.x) >> 6; it < count; it += waves) {
+    const unsigned long long item = items[it];
+    const int32_t v = (int32_t)(item >> 32);
+    const int64_t b = ptr[v] + (int64_t)(item & 0xffffffffull) * PIECE;
+    const int64_t e = min(ptr[v + 1], b + PIECE);
     unsigned long long s = 0;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += BLOCK)
-      if (rnd[nbr[j]] == ALIVE) s += (unsigned long long)(wt ? wt[j] : 1ll);
+#pragma unroll 4
+    for (int64_t j = b + lane; j < e; j += 64)
+      if (is_alive(alive, nbr[j])) s += (unsigned long long)(wt ? wt[j] : 1ll);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long t = 0;
-      for (int i = 0; i < BLOCK / 64; i++) t += s_part[i];
-      if (t) atomicAdd((unsigned long long *)&w[v], t);
-    }
-    __syncthreads();
+    if (lane == 0 && s) atomicAdd((unsigned long long *)&w[v], s);
   }
 }
 
@@ -402,6 +443,7 @@ __global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int3
   sc->sum2 = 0;
   sc->nu = sc->nu_big = 0;
   sc->deg_peel = sc->deg_keep = 0;
+  sc->nitems = 0;
   sc->cnt[1 - cl] = 0;
 }
 
@@ -427,6 +469,8 @@ struct kws_dsd_graph {
   int32_t *rnd = nullptr;          // [n] round of removal
   int32_t *list[2] = {nullptr, nullptr};
   int32_t *ul = nullptr;           // [n] peeled in the current round
+  uint32_t *alive = nullptr;       // [(n + 31) / 32] alive bits
+  unsigned long long *items = nullptr;   // [n + 2m / PIECE] pull items: vertex << 32 | piece
   kws::PeelScalars *sc = nullptr;
   int64_t *d_sizes = nullptr, *d_f = nullptr;
   int32_t d_cap = 0;
@@ -439,7 +483,7 @@ namespace {
 void dsd_release(kws_dsd_graph *g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
-  void *ps[] = {g->ptr, g->nbr, g->wt, g->a, g->big, g->w0, g->w, g->rnd, g->list[0], g->list[1], g->ul, g->sc,
+  void *ps[] = {g->ptr, g->nbr, g->wt, g->a, g->big, g->w0, g->w, g->rnd, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sc,
                 g->d_sizes, g->d_f};
   for (void *p : ps) kws::dev_free(p);
   if (g->stream) (void)hipStreamDestroy(g->stream);
@@ -570,6 +614,8 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   DSD_STEP(dev_array(&g->list[0], (size_t)n, "alive list"));
   DSD_STEP(dev_array(&g->list[1], (size_t)n, "alive list"));
   DSD_STEP(dev_array(&g->ul, (size_t)n, "peeled list"));
+  DSD_STEP(dev_array(&g->alive, ((size_t)n + 31) / 32, "alive bits"));
+  DSD_STEP(dev_array(&g->items, (size_t)n + (size_t)(2 * m) / PIECE + 1, "pull items"));
   DSD_STEP(dev_array(&g->sc, 1, "peeling scalars"));
   g->nbig = (int32_t)big.size();
   DSD_HIP(hipMemcpyAsync(g->ptr, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
@@ -645,7 +691,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   KWS_HIP(hipGetLastError());
   g->has_run = false;
   k_scalars_init<<<1, 64, 0, s>>>(g->sc, n);
-  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd, g->list[0]);
+  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd, g->list[0], g->alive);
   {
     DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
     k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
@@ -667,16 +713,15 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
         k_count_lt<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->sc, g->w);
       k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
       k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
-                                                                   g->w, g->ptr, g->rnd, p->k, p->eps_num,
-                                                                   p->eps_den);
+                                                                   g->w, g->ptr, g->rnd, g->alive, g->items, p->k,
+                                                                   p->eps_num, p->eps_den);
     }
     {
       DsdTimer t(t_upd, DSD_UPDATE, s, &evlog);
       k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, g->ptr, g->nbr, g->wt,
-                                                                            g->rnd, g->w);
+                                                                            g->alive, g->w);
       k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
-      k_update_pull<<<(unsigned)resident, BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->ptr, g->nbr, g->wt, g->rnd,
-                                                         g->w);
+      k_update_pull<<<(unsigned)resident, BLOCK, 0, s>>>(g->items, g->sc, g->ptr, g->nbr, g->wt, g->alive, g->w);
     }
     {
       DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
