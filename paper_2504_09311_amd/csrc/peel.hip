@@ -1,11 +1,17 @@
 // Densest-subgraph discovery by parallel peeling (the paper's Section 4.1,
 // Algorithm 2), with the DG, DW and FD weight functions of Section 2.1.
 //
-// Layout: every edge is stored twice in an incidence CSR (once in the row
-// of each endpoint) with its weight; per vertex the current peeling weight
-// w (int64), the round it was peeled in and an alive bit (the bitmap is
-// n/8 bytes, so the random alive tests of the update hit L2), and two
-// ping-pong lists of the vertices still alive. A step is four launches
+// Layout: vertices are renumbered at load by descending degree (ties by
+// id), so the survivors of the later rounds, the dense part, hold the
+// smallest ids; every edge is stored twice in an incidence CSR (once in the
+// row of each endpoint, rows sorted by neighbour id) with its weight and a
+// running sum of the weights; per vertex the current peeling weight w
+// (int64), the round it was peeled in (in the caller's ids) and an alive
+// bit (the bitmap is n/8 bytes, so random alive tests hit L2), and two
+// ping-pong lists of the vertices still alive. Decide also records one
+// more than the largest surviving id: neighbours at or above it are gone
+// without a test, and when the survivors are exactly the ids below it the
+// bitmap is not read at all. A step is four launches
 // (plus one thread that picks its kind), all on the device:
 //   decide  scan the alive list: w_u * |S| * den <= k * (den + num) * f
 //           (128-bit products) puts u on the peeled list, else on the next
@@ -13,16 +19,17 @@
 //           are aggregated per block;
 //   update  push: the peeled vertices subtract their edge weights from the
 //           neighbours still alive (64-bit atomics); or pull: the survivors
-//           re-sum their alive neighbours, a wavefront per row piece;
-//           push only while the peeled vertices have a small share of the
-//           incidences, as it pays an atomic per alive neighbour (chosen on
-//           the device);
+//           re-sum their alive neighbours (a binary search per survivor,
+//           or a wavefront per row piece); push only while the peeled
+//           vertices have a small share of the work, as it pays an atomic
+//           per alive neighbour (chosen on the device);
 //   reduce  sum of a + w over the survivors (= 2 f(S_i));
 //   end     one thread: f, |S|, the per-round record and the densest S_i.
 // The host only enqueues rounds and reads |S| every few rounds to stop.
 // Everything is integer arithmetic, so results do not depend on the order
 // of the atomics.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -44,7 +51,7 @@ constexpr int PIECE = 1024;     // incidences of a survivor's row summed by one 
 // push costs an atomic per alive neighbour, pull streams ids and tests a bit:
 // push is taken while the removed vertices have at most 1/PUSH_COST of the
 // survivors' incidences
-constexpr unsigned long long PUSH_COST = 4;
+constexpr unsigned long long PUSH_COST = 16;
 
 // Kinds of step: a peeling step opens a round (Algorithm 2's test, or the
 // thresholds of Algorithms 3 and 4); a trimming step (Algorithm 4) removes
@@ -66,24 +73,34 @@ struct PeelScalars {
   unsigned long long tau_lo, tau_hi, tau_den;   // tau_max = (tau_hi:tau_lo) / tau_den
   long long f, s;              // f(S), |S| of the current set
   long long best_f, best_s;
-  int best_i, round, phase, pad;
+  int best_i, round, phase;
+  int bound;                   // 1 + the largest id among the survivors of the current step
 };
 
-__global__ __launch_bounds__(BLOCK) void k_scatter(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                                                   const int64_t *__restrict__ ew, int64_t m, int metric,
-                                                   const int64_t *__restrict__ fd_table,
-                                                   const int32_t *__restrict__ deg, unsigned long long *fill,
-                                                   int32_t *__restrict__ nbr, int64_t *__restrict__ wt) {
+// incidence keys of the relabelled graph, (row << 32) | neighbour, one
+// from each end of every edge, with the edge weight as value: sorted, they
+// give every row in order of neighbour id
+__global__ __launch_bounds__(BLOCK) void k_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                                                const int64_t *__restrict__ ew, int64_t m, int metric,
+                                                const int64_t *__restrict__ fd_table,
+                                                const int32_t *__restrict__ deg, const int32_t *__restrict__ inv,
+                                                unsigned long long *__restrict__ keys, int64_t *__restrict__ vals) {
   for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < m; e += (int64_t)gridDim.x * BLOCK) {
-    const int32_t u = src[e], v = dst[e];
-    int64_t c = 1;
-    if (metric == KWS_DSD_DW) c = ew[e];
-    else if (metric == KWS_DSD_FD) c = fd_table[deg[u]];
-    const unsigned long long p = atomicAdd(&fill[u], 1ull), q = atomicAdd(&fill[v], 1ull);
-    nbr[p] = v;
-    nbr[q] = u;
-    if (wt) { wt[p] = c; wt[q] = c; }
+    const int32_t u = inv[src[e]], v = inv[dst[e]];
+    keys[2 * e] = ((unsigned long long)u << 32) | (uint32_t)v;
+    keys[2 * e + 1] = ((unsigned long long)v << 32) | (uint32_t)u;
+    if (vals) {
+      const int64_t c = metric == KWS_DSD_DW ? ew[e] : fd_table[deg[u]];   // FD: by the source's degree
+      vals[2 * e] = c;
+      vals[2 * e + 1] = c;
+    }
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_unpack(const unsigned long long *__restrict__ keys, int64_t count,
+                                                  int32_t *__restrict__ nbr) {
+  for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < count; j += (int64_t)gridDim.x * BLOCK)
+    nbr[j] = (int32_t)(uint32_t)keys[j];
 }
 
 // initial peeling weights: a_u plus the weights of all incident edges
@@ -141,6 +158,7 @@ __global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
     sc->best_s = 1;
     sc->round = 0;
     sc->phase = STEP_PEEL;
+    sc->bound = n;
   }
 }
 
@@ -148,7 +166,16 @@ __device__ __forceinline__ u128 tau_num(const PeelScalars *sc) {
   return ((u128)sc->tau_hi << 64) | (u128)sc->tau_lo;
 }
 
-__device__ __forceinline__ bool pull_step(const PeelScalars *sc) {
+// the survivors are exactly the ids below bound (distinct ids, as many as
+// the bound): then a vertex is alive iff its id is below the bound
+__device__ __forceinline__ bool prefix_alive(const PeelScalars *sc, int cb) {
+  return sc->cnt[cb] == (unsigned long long)sc->bound;
+}
+
+// pull re-sums the survivors' rows; with prefix survivors that is one
+// binary search per survivor, otherwise a pass over their rows
+__device__ __forceinline__ bool pull_step(const PeelScalars *sc, int cb) {
+  if (prefix_alive(sc, cb)) return sc->deg_peel > sc->cnt[cb];
   return sc->deg_peel * PUSH_COST > sc->deg_keep;
 }
 
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
                                                   int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
                                                   int32_t n_total, PeelScalars *sc, const int64_t *__restrict__ w,
                                                   const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd,
-                                                  uint32_t *__restrict__ alive,
+                                                  const int32_t *__restrict__ perm, uint32_t *__restrict__ alive,
                                                   unsigned long long *__restrict__ items,
                                                   int32_t k, int32_t num, int32_t den) {
   __shared__ unsigned s_w[BLOCK / 64];
@@ -275,6 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
   const u128 rhs = trim ? (u128)(uint64_t)sc->f : (u128)(uint64_t)k * (u128)(uint64_t)(den + num) * (u128)(uint64_t)sc->f;
   const u128 scale = trim ? (u128)(uint64_t)sc->s : (u128)(uint64_t)sc->s * (u128)(uint64_t)den;
   const u128 tau = tau_num(sc), tden = (u128)sc->tau_den;
+  int32_t top = 0;   // 1 + the largest surviving id seen by this thread
   for (unsigned long long c0 = (unsigned long long)blockIdx.x * CHUNK; c0 < count;
        c0 += (unsigned long long)gridDim.x * CHUNK) {
     int32_t v[PER];
@@ -331,15 +359,18 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
       clear_alive(alive, v[j], (peel_bits >> j) & 1u);
       if (v[j] < 0) continue;
       if ((peel_bits >> j) & 1u) {
-        rnd[v[j]] = round;
+        rnd[perm[v[j]]] = round;   // rounds are kept in the caller's ids
         if ((big_bits >> j) & 1u) ul[n_total - 1 - pb++] = v[j];   // large rows fill the list from its end
         else ul[pu++] = v[j];
       } else {
         lb[pk++] = v[j];
+        top = max(top, v[j] + 1);
         for (uint32_t q = 0; q < pcs[j]; q++) items[pi++] = ((unsigned long long)v[j] << 32) | q;
       }
     }
   }
+  for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
+  if ((threadIdx.x & 63) == 0 && top) atomicMax(&sc->bound, top);
 }
 
 // push: the removed vertices subtract their edge weights from the
@@ -347,18 +378,21 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
 // wavefront per vertex with a large one. Runs while the removed vertices
 // have few incidences next to the survivors' (pull_step).
 __global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict__ ul, int32_t n_total,
-                                                       PeelScalars *sc, const int64_t *__restrict__ ptr,
+                                                       PeelScalars *sc, int cb, const int64_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ nbr,
                                                        const int64_t *__restrict__ wt,
                                                        const uint32_t *__restrict__ alive, int64_t *__restrict__ w) {
-  if (pull_step(sc)) return;
+  if (pull_step(sc, cb)) return;
   const unsigned long long nu = sc->nu, nb = sc->nu_big;
+  const int32_t bound = sc->bound;
+  const bool prefix = prefix_alive(sc, cb);
   for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < nu;
        i += (unsigned long long)gridDim.x * BLOCK) {
     const int32_t u = ul[i];
     for (int64_t j = ptr[u]; j < ptr[u + 1]; j++) {
       const int32_t x = nbr[j];
-      if (is_alive(alive, x)) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
+      if (x < bound && (prefix || is_alive(alive, x)))
+        atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
     }
   }
   const int lane = threadIdx.x & 63;
@@ -368,31 +402,59 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict
     const int64_t b = ptr[u], e = ptr[u + 1];
     for (int64_t j = b + lane; j < e; j += 64) {
       const int32_t x = nbr[j];
-      if (is_alive(alive, x)) atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
+      if (x < bound && (prefix || is_alive(alive, x)))
+        atomicAdd((unsigned long long *)&w[x], (unsigned long long)(-(wt ? wt[j] : 1ll)));
     }
   }
 }
 
-// pull: the survivors' weights restart from a, and each piece of PIECE
-// incidences of a survivor's row (listed by decide) is summed over the
-// alive neighbours by one wavefront and added with one atomic, so hub rows
-// spread over many wavefronts.
+// pull: the survivors' weights restart from a. When the survivors are the
+// ids below the bound (as the degree order makes them after DG's rounds),
+// a survivor's alive neighbours are the head of its sorted row: a binary
+// search finds its end, and the weight is its length (DG) or a difference
+// of the running weight sums. Otherwise each piece of PIECE incidences of a
+// survivor's row (listed by decide) is summed over the alive neighbours by
+// one wavefront and added with one atomic, so hub rows spread over many
+// wavefronts.
 __global__ __launch_bounds__(BLOCK) void k_update_pull_reset(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
-                                                             const int64_t *__restrict__ a, int64_t *__restrict__ w) {
-  if (!pull_step(sc)) return;
+                                                             const int64_t *__restrict__ a,
+                                                             const int64_t *__restrict__ ptr,
+                                                             const int32_t *__restrict__ nbr,
+                                                             const int64_t *__restrict__ wcum,
+                                                             int64_t *__restrict__ w) {
+  if (!pull_step(sc, cb)) return;
   const unsigned long long count = sc->cnt[cb];
+  const bool prefix = prefix_alive(sc, cb);
+  const int32_t bound = sc->bound;
   for (unsigned long long i = (unsigned long long)blockIdx.x * BLOCK + threadIdx.x; i < count;
-       i += (unsigned long long)gridDim.x * BLOCK)
-    w[lb[i]] = a ? a[lb[i]] : 0;
+       i += (unsigned long long)gridDim.x * BLOCK) {
+    const int32_t v = lb[i];
+    int64_t x = a ? a[v] : 0;
+    if (prefix) {
+      // rows are sorted: the alive neighbours are the entries below the bound
+      const int64_t b = ptr[v];
+      int64_t lo = b, hi = ptr[v + 1];
+      while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (nbr[mid] < bound) lo = mid + 1;
+        else hi = mid;
+      }
+      if (!wcum) x += lo - b;
+      else if (lo > b) x += wcum[lo - 1] - (b > 0 ? wcum[b - 1] : 0);
+    }
+    w[v] = x;
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_update_pull(const unsigned long long *__restrict__ items, PeelScalars *sc,
+                                                       int cb,
                                                        const int64_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ nbr,
                                                        const int64_t *__restrict__ wt,
                                                        const uint32_t *__restrict__ alive, int64_t *__restrict__ w) {
-  if (!pull_step(sc)) return;
+  if (!pull_step(sc, cb) || prefix_alive(sc, cb)) return;   // prefix survivors: done by the reset
   const unsigned long long count = sc->nitems;
+  const int32_t bound = sc->bound;
   const int lane = threadIdx.x & 63;
   const unsigned long long waves = ((unsigned long long)gridDim.x * BLOCK) >> 6;
   for (unsigned long long it = ((unsigned long long)blockIdx.x * BLOCK + threadIdx.x) >> 6; it < count; it += waves) {
@@ -400,10 +462,17 @@ __global__ __launch_bounds__(BLOCK) void k_update_pull(const unsigned long long 
     const int32_t v = (int32_t)(item >> 32);
     const int64_t b = ptr[v] + (int64_t)(item & 0xffffffffull) * PIECE;
     const int64_t e = min(ptr[v + 1], b + PIECE);
+    if (nbr[b] >= bound) continue;   // rows are sorted: every neighbour in the piece is gone
     unsigned long long s = 0;
-#pragma unroll 4
-    for (int64_t j = b + lane; j < e; j += 64)
-      if (is_alive(alive, nbr[j])) s += (unsigned long long)(wt ? wt[j] : 1ll);
+    int32_t xs[PIECE / 64];
+#pragma unroll
+    for (int t = 0; t < PIECE / 64; t++) {
+      const int64_t j = b + lane + 64 * t;
+      xs[t] = j < e ? nbr[j] : bound;
+    }
+#pragma unroll
+    for (int t = 0; t < PIECE / 64; t++)
+      if (xs[t] < bound && is_alive(alive, xs[t])) s += (unsigned long long)(wt ? wt[b + lane + 64 * t] : 1ll);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0 && s) atomicAdd((unsigned long long *)&w[v], s);
   }
@@ -444,6 +513,7 @@ __global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int3
   sc->nu = sc->nu_big = 0;
   sc->deg_peel = sc->deg_keep = 0;
   sc->nitems = 0;
+  sc->bound = 0;
   sc->cnt[1 - cl] = 0;
 }
 
@@ -461,12 +531,14 @@ struct kws_dsd_graph {
   int64_t *ptr = nullptr;          // [n + 1] incidence offsets
   int32_t *nbr = nullptr;          // [2m]
   int64_t *wt = nullptr;           // [2m] edge weights (none for DG)
+  int64_t *wcum = nullptr;         // [2m] running sum of wt over all rows (none for DG)
   int64_t *a = nullptr;            // [n] vertex weights (FD only)
   int32_t *big = nullptr;          // vertices whose row is summed by a wavefront
   int32_t nbig = 0;
   int64_t *w0 = nullptr;           // [n] peeling weights in G (start of every run)
   int64_t *w = nullptr;            // [n] peeling weights
-  int32_t *rnd = nullptr;          // [n] round of removal
+  int32_t *rnd = nullptr;          // [n] round of removal, in the caller's ids
+  int32_t *perm = nullptr;         // [n] caller's id of each internal id
   int32_t *list[2] = {nullptr, nullptr};
   int32_t *ul = nullptr;           // [n] peeled in the current round
   uint32_t *alive = nullptr;       // [(n + 31) / 32] alive bits
@@ -483,7 +555,7 @@ namespace {
 void dsd_release(kws_dsd_graph *g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
-  void *ps[] = {g->ptr, g->nbr, g->wt, g->a, g->big, g->w0, g->w, g->rnd, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sc,
+  void *ps[] = {g->ptr, g->nbr, g->wt, g->wcum, g->a, g->big, g->w0, g->w, g->rnd, g->perm, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sc,
                 g->d_sizes, g->d_f};
   for (void *p : ps) kws::dev_free(p);
   if (g->stream) (void)hipStreamDestroy(g->stream);
@@ -579,11 +651,32 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
     fd_table.resize((size_t)maxdeg + 1);
     for (int32_t x = 0; x <= maxdeg; x++) fd_table[x] = std::llround(16777216.0 / std::log((double)x + 5.0));
   }
+  // Internal ids by descending degree (ties by id): the survivors of the
+  // later rounds, the dense part, get the smallest ids, so their alive bits
+  // and weights sit together and a sorted row holds them at its start.
+  std::vector<int32_t> perm((size_t)n), inv((size_t)n);
+  {
+    std::vector<int64_t> at((size_t)maxdeg + 2, 0);
+    for (int32_t v = 0; v < n; v++) at[(size_t)(maxdeg - deg[v]) + 1]++;
+    for (size_t b = 1; b < at.size(); b++) at[b] += at[b - 1];
+    for (int32_t v = 0; v < n; v++) {
+      const int64_t pos = at[(size_t)(maxdeg - deg[v])]++;
+      perm[(size_t)pos] = v;
+      inv[(size_t)v] = (int32_t)pos;
+    }
+  }
+  std::vector<int32_t> ideg((size_t)n);
   std::vector<int64_t> ptr((size_t)n + 1, 0);
   std::vector<int32_t> big;
-  for (int32_t v = 0; v < n; v++) {
-    ptr[v + 1] = ptr[v] + deg[v];
-    if (deg[v] > SMALL_DEG) big.push_back(v);
+  for (int32_t i = 0; i < n; i++) {
+    ideg[(size_t)i] = deg[(size_t)perm[(size_t)i]];
+    ptr[i + 1] = ptr[i] + ideg[(size_t)i];
+    if (ideg[(size_t)i] > SMALL_DEG) big.push_back(i);
+  }
+  std::vector<int64_t> ia;
+  if (d->metric == KWS_DSD_FD) {
+    ia.resize((size_t)n);
+    for (int32_t i = 0; i < n; i++) ia[(size_t)i] = d->vertex_w[perm[(size_t)i]];
   }
 
   kws_dsd_graph *g = new kws_dsd_graph();
@@ -595,11 +688,13 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
     return bail(fail(KWS_EDEVICE, "stream creation failed"));
   hipStream_t s = g->stream;
   kws_status st = KWS_OK;
-  int32_t *d_src = nullptr, *d_dst = nullptr, *d_deg = nullptr;
-  int64_t *d_ew = nullptr, *d_fd = nullptr;
-  unsigned long long *d_fill = nullptr;
+  int32_t *d_src = nullptr, *d_dst = nullptr, *d_deg = nullptr, *d_inv = nullptr;
+  int64_t *d_ew = nullptr, *d_fd = nullptr, *d_vals = nullptr;
+  unsigned long long *d_keys = nullptr, *d_sorted = nullptr;
+  void *d_tmp = nullptr;
   auto cleanup = [&]() {
-    dev_free(d_src); dev_free(d_dst); dev_free(d_deg); dev_free(d_ew); dev_free(d_fd); dev_free(d_fill);
+    dev_free(d_src); dev_free(d_dst); dev_free(d_deg); dev_free(d_inv); dev_free(d_ew); dev_free(d_fd);
+    dev_free(d_vals); dev_free(d_keys); dev_free(d_sorted); dev_free(d_tmp);
   };
 #define DSD_STEP(x) do { st = (x); if (st != KWS_OK) { cleanup(); return bail(st); } } while (0)
 #define DSD_HIP(x) DSD_STEP((x) == hipSuccess ? KWS_OK : fail(KWS_EDEVICE, "%s failed", #x))
@@ -611,6 +706,7 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   DSD_STEP(dev_array(&g->w0, (size_t)n, "initial peeling weights"));
   DSD_STEP(dev_array(&g->w, (size_t)n, "peeling weights"));
   DSD_STEP(dev_array(&g->rnd, (size_t)n, "peel rounds"));
+  DSD_STEP(dev_array(&g->perm, (size_t)n, "id map"));
   DSD_STEP(dev_array(&g->list[0], (size_t)n, "alive list"));
   DSD_STEP(dev_array(&g->list[1], (size_t)n, "alive list"));
   DSD_STEP(dev_array(&g->ul, (size_t)n, "peeled list"));
@@ -619,15 +715,19 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   DSD_STEP(dev_array(&g->sc, 1, "peeling scalars"));
   g->nbig = (int32_t)big.size();
   DSD_HIP(hipMemcpyAsync(g->ptr, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+  if (n > 0) DSD_HIP(hipMemcpyAsync(g->perm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
   if (!big.empty()) DSD_HIP(hipMemcpyAsync(g->big, big.data(), sizeof(int32_t) * big.size(), hipMemcpyHostToDevice, s));
-  if (g->a) DSD_HIP(hipMemcpyAsync(g->a, d->vertex_w, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  if (g->a) DSD_HIP(hipMemcpyAsync(g->a, ia.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, s));
   if (m > 0) {
+    const size_t inc = (size_t)(2 * m);
     DSD_STEP(dev_array(&d_src, (size_t)m, "edge sources"));
     DSD_STEP(dev_array(&d_dst, (size_t)m, "edge targets"));
-    DSD_STEP(dev_array(&d_fill, (size_t)n + 1, "fill counters"));
+    DSD_STEP(dev_array(&d_inv, (size_t)n, "id map"));
+    DSD_STEP(dev_array(&d_keys, inc, "incidence keys"));
+    DSD_STEP(dev_array(&d_sorted, inc, "sorted incidence keys"));
     DSD_HIP(hipMemcpyAsync(d_src, d->src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
     DSD_HIP(hipMemcpyAsync(d_dst, d->dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
-    DSD_HIP(hipMemcpyAsync(d_fill, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    DSD_HIP(hipMemcpyAsync(d_inv, inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     if (d->metric == KWS_DSD_DW) {
       DSD_STEP(dev_array(&d_ew, (size_t)m, "edge weights"));
       DSD_HIP(hipMemcpyAsync(d_ew, d->edge_w, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, s));
@@ -636,11 +736,41 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
       DSD_STEP(dev_array(&d_fd, fd_table.size(), "FD weight table"));
       DSD_STEP(dev_array(&d_deg, (size_t)n, "degrees"));
       DSD_HIP(hipMemcpyAsync(d_fd, fd_table.data(), sizeof(int64_t) * fd_table.size(), hipMemcpyHostToDevice, s));
-      DSD_HIP(hipMemcpyAsync(d_deg, deg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+      DSD_HIP(hipMemcpyAsync(d_deg, ideg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     }
-    k_scatter<<<grid_for(m, BLOCK, 65536), BLOCK, 0, s>>>(d_src, d_dst, d_ew, m, d->metric, d_fd, d_deg, d_fill,
-                                                          g->nbr, g->wt);
+    if (g->wt) DSD_STEP(dev_array(&d_vals, inc, "incidence weight keys"));
+    k_keys<<<grid_for(m, BLOCK, 65536), BLOCK, 0, s>>>(d_src, d_dst, d_ew, m, d->metric, d_fd, d_deg, d_inv, d_keys,
+                                                       d_vals);
     DSD_HIP(hipGetLastError());
+    // sort by (row, neighbour): 32 bits of neighbour and the bits of a row id
+    int end_bit = 32;
+    while (end_bit < 64 && ((int64_t)1 << (end_bit - 32)) < (int64_t)n) end_bit++;
+    size_t tmp_bytes = 0;
+    if (g->wt) {
+      DSD_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_keys, d_sorted, d_vals, g->wt, inc, 0, end_bit, s));
+      DSD_STEP(dev_array((char **)&d_tmp, tmp_bytes, "sort scratch"));
+      DSD_HIP(hipcub::DeviceRadixSort::SortPairs(d_tmp, tmp_bytes, d_keys, d_sorted, d_vals, g->wt, inc, 0, end_bit, s));
+    } else {
+      DSD_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, d_keys, d_sorted, inc, 0, end_bit, s));
+      DSD_STEP(dev_array((char **)&d_tmp, tmp_bytes, "sort scratch"));
+      DSD_HIP(hipcub::DeviceRadixSort::SortKeys(d_tmp, tmp_bytes, d_keys, d_sorted, inc, 0, end_bit, s));
+    }
+    k_unpack<<<grid_for((int64_t)inc, BLOCK, 65536), BLOCK, 0, s>>>(d_sorted, (int64_t)inc, g->nbr);
+    DSD_HIP(hipGetLastError());
+    if (g->wt) {
+      // running sum of the weights in CSR order: a row prefix's weight is a
+      // difference of two entries (totals stay below 2^55)
+      DSD_STEP(dev_array(&g->wcum, inc, "incidence weight sums"));
+      size_t scan_bytes = 0;
+      DSD_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, g->wt, g->wcum, inc, s));
+      if (scan_bytes > tmp_bytes) {
+        DSD_HIP(hipStreamSynchronize(s));
+        dev_free(d_tmp);
+        d_tmp = nullptr;
+        DSD_STEP(dev_array((char **)&d_tmp, scan_bytes, "scan scratch"));
+      }
+      DSD_HIP(hipcub::DeviceScan::InclusiveSum(d_tmp, scan_bytes, g->wt, g->wcum, inc, s));
+    }
   }
   k_w0_small<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->ptr, g->wt, g->a, g->w0);
   if (g->nbig && g->wt)
@@ -713,15 +843,16 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
         k_count_lt<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->sc, g->w);
       k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
       k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
-                                                                   g->w, g->ptr, g->rnd, g->alive, g->items, p->k,
+                                                                   g->w, g->ptr, g->rnd, g->perm, g->alive, g->items, p->k,
                                                                    p->eps_num, p->eps_den);
     }
     {
       DsdTimer t(t_upd, DSD_UPDATE, s, &evlog);
-      k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, g->ptr, g->nbr, g->wt,
-                                                                            g->alive, g->w);
-      k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
-      k_update_pull<<<(unsigned)resident, BLOCK, 0, s>>>(g->items, g->sc, g->ptr, g->nbr, g->wt, g->alive, g->w);
+      k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, cb, g->ptr, g->nbr,
+                                                                            g->wt, g->alive, g->w);
+      k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->ptr,
+                                                                             g->nbr, g->wcum, g->w);
+      k_update_pull<<<(unsigned)resident, BLOCK, 0, s>>>(g->items, g->sc, cb, g->ptr, g->nbr, g->wt, g->alive, g->w);
     }
     {
       DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
