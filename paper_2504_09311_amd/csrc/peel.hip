@@ -48,6 +48,7 @@ constexpr int32_t ALIVE = KWS_DSD_ALIVE;
 constexpr int SMALL_DEG = 64;   // rows above this are summed by a wavefront at start
 constexpr int SMALL_PUSH = 16;  // peeled rows up to this are pushed by one thread
 constexpr int PIECE = 1024;     // incidences of a survivor's row summed by one wavefront (pull)
+constexpr uint32_t FEW_PIECES = 4;   // rows of more pieces are listed by the whole wavefront
 // push costs an atomic per alive neighbour, pull streams ids and tests a bit:
 // push is taken while the removed vertices have at most 1/PUSH_COST of the
 // survivors' incidences
@@ -60,21 +61,24 @@ constexpr unsigned long long PUSH_COST = 16;
 enum { STEP_PEEL = 0, STEP_TRIM = 1, STEP_DONE = 2 };
 enum { MODE_PLAIN = 0, MODE_GPO = 1, MODE_LPO = 2 };
 
+// Every counter that blocks add to atomically has a 128-byte line of its
+// own: atomics on one line are serialised, on separate lines they proceed
+// in parallel.
 struct PeelScalars {
-  unsigned long long cnt[2];   // lengths of the two alive lists
-  unsigned long long nu;       // vertices removed by the current step with small rows
-  unsigned long long nu_big;   // ... with rows above SMALL_PUSH incidences (listed from the end)
-  unsigned long long sum2;     // sum of a + w over the survivors
-  unsigned long long deg_peel; // incidences of the vertices removed by the current step
-  unsigned long long deg_keep; // incidences of the survivors
-  unsigned long long nlt;      // survivors with w_u < g(S) (trimming test)
-  unsigned long long nitems;   // pull work items (row pieces of the survivors)
-  unsigned long long trims;    // trimming steps so far
+  alignas(128) unsigned long long cnt[2];   // lengths of the two alive lists
+  alignas(128) unsigned long long nu;       // vertices removed by the current step with small rows
+  alignas(128) unsigned long long nu_big;   // ... with rows above SMALL_PUSH incidences (listed from the end)
+  alignas(128) unsigned long long sum2;     // sum of a + w over the survivors
+  alignas(128) unsigned long long deg_peel; // incidences of the vertices removed by the current step
+  alignas(128) unsigned long long deg_keep; // incidences of the survivors
+  alignas(128) unsigned long long nlt;      // survivors with w_u < g(S) (trimming test)
+  alignas(128) unsigned long long nitems;   // pull work items (row pieces of the survivors)
+  alignas(128) int bound;                   // 1 + the largest id among the survivors of the current step
+  alignas(128) unsigned long long trims;    // trimming steps so far
   unsigned long long tau_lo, tau_hi, tau_den;   // tau_max = (tau_hi:tau_lo) / tau_den
   long long f, s;              // f(S), |S| of the current set
   long long best_f, best_s;
   int best_i, round, phase;
-  int bound;                   // 1 + the largest id among the survivors of the current step
 };
 
 // incidence keys of the relabelled graph, (row << 32) | neighbour, one
@@ -278,19 +282,19 @@ __device__ __forceinline__ unsigned block_excl_scan(unsigned x, unsigned *s_w, u
 // strided so loads coalesce), tests each, and appends the peeled and the
 // surviving ones with one reservation per list and chunk; the degree sums
 // of both sets choose how the weights are updated. A removed vertex gets
-// its round and loses its alive bit; a survivor's row is listed in pieces
-// of PIECE incidences for the pull.
-constexpr int PER = 16, CHUNK = PER * BLOCK;
+// its round and loses its alive bit.
+constexpr int PER = 8, CHUNK = PER * BLOCK;
 
 __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la, int ca,
                                                   int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
                                                   int32_t n_total, PeelScalars *sc, const int64_t *__restrict__ w,
                                                   const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd,
                                                   const int32_t *__restrict__ perm, uint32_t *__restrict__ alive,
-                                                  unsigned long long *__restrict__ items,
                                                   int32_t k, int32_t num, int32_t den) {
   __shared__ unsigned s_w[BLOCK / 64];
-  __shared__ unsigned long long s_base[4];
+  __shared__ unsigned long long s_base[3];
+  __shared__ unsigned long long s_deg[2][BLOCK / 64];
+  __shared__ int s_top[BLOCK / 64];
   const int phase = sc->phase;
   if (phase == STEP_DONE) return;
   const int32_t round = sc->round;
@@ -302,13 +306,12 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
   const u128 rhs = trim ? (u128)(uint64_t)sc->f : (u128)(uint64_t)k * (u128)(uint64_t)(den + num) * (u128)(uint64_t)sc->f;
   const u128 scale = trim ? (u128)(uint64_t)sc->s : (u128)(uint64_t)sc->s * (u128)(uint64_t)den;
   const u128 tau = tau_num(sc), tden = (u128)sc->tau_den;
-  int32_t top = 0;   // 1 + the largest surviving id seen by this thread
+  int32_t top = 0;                  // 1 + the largest surviving id seen by this thread
+  unsigned long long dp = 0, dk = 0;   // incidences of its removed and surviving vertices
   for (unsigned long long c0 = (unsigned long long)blockIdx.x * CHUNK; c0 < count;
        c0 += (unsigned long long)gridDim.x * CHUNK) {
     int32_t v[PER];
-    uint32_t pcs[PER];   // pieces of a survivor's row
-    unsigned peel_bits = 0, big_bits = 0, np = 0, nb = 0, nk = 0, ni = 0;
-    unsigned long long dp = 0, dk = 0;
+    unsigned peel_bits = 0, big_bits = 0, np = 0, nb = 0, nk = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       const unsigned long long idx = c0 + (unsigned long long)j * BLOCK + threadIdx.x;
@@ -316,7 +319,6 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
     }
 #pragma unroll
     for (int j = 0; j < PER; j++) {
-      pcs[j] = 0;
       if (v[j] < 0) continue;
       const unsigned long long d = (unsigned long long)(ptr[v[j] + 1] - ptr[v[j]]);
       const u128 wv = (u128)(uint64_t)w[v[j]];
@@ -328,31 +330,19 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
       } else {
         nk++;
         dk += d;
-        pcs[j] = (uint32_t)((d + PIECE - 1) / PIECE);
-        ni += pcs[j];
       }
     }
-    unsigned tp, tb, tk, ti;
+    unsigned tp, tb, tk;
     const unsigned op = block_excl_scan(np, s_w, &tp);
     const unsigned ob = block_excl_scan(nb, s_w, &tb);
     const unsigned ok = block_excl_scan(nk, s_w, &tk);
-    const unsigned oi = block_excl_scan(ni, s_w, &ti);
-    for (int off = 32; off > 0; off >>= 1) {
-      dp += __shfl_xor(dp, off);
-      dk += __shfl_xor(dk, off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      if (dp) atomicAdd(&sc->deg_peel, dp);
-      if (dk) atomicAdd(&sc->deg_keep, dk);
-    }
     if (threadIdx.x == 0) {
       s_base[0] = tp ? atomicAdd(&sc->nu, (unsigned long long)tp) : 0ull;
       s_base[1] = tk ? atomicAdd(&sc->cnt[cb], (unsigned long long)tk) : 0ull;
       s_base[2] = tb ? atomicAdd(&sc->nu_big, (unsigned long long)tb) : 0ull;
-      s_base[3] = ti ? atomicAdd(&sc->nitems, (unsigned long long)ti) : 0ull;
     }
     __syncthreads();
-    unsigned long long pu = s_base[0] + op, pk = s_base[1] + ok, pb = s_base[2] + ob, pi = s_base[3] + oi;
+    unsigned long long pu = s_base[0] + op, pk = s_base[1] + ok, pb = s_base[2] + ob;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < PER; j++) {
@@ -365,12 +355,80 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
       } else {
         lb[pk++] = v[j];
         top = max(top, v[j] + 1);
-        for (uint32_t q = 0; q < pcs[j]; q++) items[pi++] = ((unsigned long long)v[j] << 32) | q;
       }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off));
-  if ((threadIdx.x & 63) == 0 && top) atomicMax(&sc->bound, top);
+  // the block's degree totals and largest survivor, one atomic each
+  for (int off = 32; off > 0; off >>= 1) {
+    dp += __shfl_xor(dp, off);
+    dk += __shfl_xor(dk, off);
+    top = max(top, __shfl_xor(top, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_deg[0][threadIdx.x >> 6] = dp;
+    s_deg[1][threadIdx.x >> 6] = dk;
+    s_top[threadIdx.x >> 6] = top;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0;
+    int t = 0;
+    for (int i = 0; i < BLOCK / 64; i++) {
+      a += s_deg[0][i];
+      b += s_deg[1][i];
+      t = max(t, s_top[i]);
+    }
+    if (a) atomicAdd(&sc->deg_peel, a);
+    if (b) atomicAdd(&sc->deg_keep, b);
+    if (t) atomicMax(&sc->bound, t);
+  }
+}
+
+// the pull's work list when the survivors are not the ids below the bound:
+// every survivor's row in pieces of PIECE incidences (a row of many pieces
+// is listed by the whole wavefront); reserved once per block and chunk
+constexpr int IPER = 4, ICHUNK = IPER * BLOCK;
+__global__ __launch_bounds__(BLOCK) void k_items(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+                                                 const int64_t *__restrict__ ptr,
+                                                 unsigned long long *__restrict__ items) {
+  __shared__ unsigned s_w[BLOCK / 64];
+  __shared__ unsigned long long s_base;
+  if (!pull_step(sc, cb) || prefix_alive(sc, cb)) return;
+  const unsigned long long count = sc->cnt[cb];
+  for (unsigned long long c0 = (unsigned long long)blockIdx.x * ICHUNK; c0 < count;
+       c0 += (unsigned long long)gridDim.x * ICHUNK) {
+    int32_t v[IPER];
+    uint32_t pcs[IPER];
+    unsigned ni = 0;
+#pragma unroll
+    for (int j = 0; j < IPER; j++) {
+      const unsigned long long idx = c0 + (unsigned long long)j * BLOCK + threadIdx.x;
+      v[j] = idx < count ? lb[idx] : -1;
+      pcs[j] = v[j] < 0 ? 0u : (uint32_t)((ptr[v[j] + 1] - ptr[v[j]] + PIECE - 1) / PIECE);
+      ni += pcs[j];
+    }
+    unsigned ti;
+    const unsigned oi = block_excl_scan(ni, s_w, &ti);
+    if (threadIdx.x == 0) s_base = ti ? atomicAdd(&sc->nitems, (unsigned long long)ti) : 0ull;
+    __syncthreads();
+    unsigned long long pi = s_base + oi;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPER; j++) {
+      const bool many = pcs[j] > FEW_PIECES;
+      unsigned long long first = pi;
+      if (many) pi += pcs[j];
+      else
+        for (uint32_t q = 0; q < pcs[j]; q++) items[pi++] = ((unsigned long long)v[j] << 32) | q;
+      for (unsigned long long ball = __ballot(many); ball; ball &= ball - 1) {
+        const int l = __ffsll((unsigned long long)ball) - 1;
+        const unsigned long long row = (unsigned long long)(uint32_t)__shfl(v[j], l) << 32;
+        const unsigned long long at = __shfl(first, l);
+        const uint32_t cnt = __shfl(pcs[j], l);
+        for (uint32_t q = threadIdx.x & 63; q < cnt; q += 64) items[at + q] = row | q;
+      }
+    }
+  }
 }
 
 // push: the removed vertices subtract their edge weights from the
@@ -837,17 +895,18 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     if (step > (int64_t)n + 1) return fail(KWS_EDEVICE, "peeling did not finish in %d steps", n + 1);
     step++;
     const int ca = (int)((step - 1) & 1), cb = (int)(step & 1);
+    if (p->mode == KWS_DSD_LPO)
+      k_count_lt<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->sc, g->w);
+    k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
     {
       DsdTimer t(t_dec, DSD_DECIDE, s, &evlog);
-      if (p->mode == KWS_DSD_LPO)
-        k_count_lt<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->sc, g->w);
-      k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
       k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
-                                                                   g->w, g->ptr, g->rnd, g->perm, g->alive, g->items, p->k,
+                                                                   g->w, g->ptr, g->rnd, g->perm, g->alive, p->k,
                                                                    p->eps_num, p->eps_den);
     }
     {
       DsdTimer t(t_upd, DSD_UPDATE, s, &evlog);
+      k_items<<<grid_for(known, ICHUNK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->ptr, g->items);
       k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, cb, g->ptr, g->nbr,
                                                                             g->wt, g->alive, g->w);
       k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->ptr,
