@@ -1,8 +1,8 @@
 // Densest-subgraph discovery by parallel peeling (the paper's Section 4.1,
 // Algorithm 2), with the DG, DW and FD weight functions of Section 2.1.
 //
-// Layout: vertices are renumbered at load by descending degree (ties by
-// id), so the survivors of the later rounds, the dense part, hold the
+// Layout: vertices are renumbered at load by descending initial peeling
+// weight (ties by id), so the survivors of the later rounds, the dense part, hold the
 // smallest ids; every edge is stored twice in an incidence CSR (once in the
 // row of each endpoint, rows sorted by neighbour id) with its weight and a
 // running sum of the weights; per vertex the current peeling weight w
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict
 }
 
 // pull: the survivors' weights restart from a. When the survivors are the
-// ids below the bound (as the degree order makes them after DG's rounds),
+// ids below the bound (as the renumbering makes them after the first round),
 // a survivor's alive neighbours are the head of its sorted row: a binary
 // search finds its end, and the weight is its length (DG) or a difference
 // of the running weight sums. Otherwise each piece of PIECE incidences of a
@@ -709,19 +709,42 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
     fd_table.resize((size_t)maxdeg + 1);
     for (int32_t x = 0; x <= maxdeg; x++) fd_table[x] = std::llround(16777216.0 / std::log((double)x + 5.0));
   }
-  // Internal ids by descending degree (ties by id): the survivors of the
-  // later rounds, the dense part, get the smallest ids, so their alive bits
-  // and weights sit together and a sorted row holds them at its start.
+  // Internal ids by descending initial peeling weight w_u(V) (ties by id):
+  // the first round keeps exactly the heaviest vertices, so its survivors
+  // are the smallest ids, and the later rounds' survivors, the dense part,
+  // stay among them; their alive bits and weights sit together and a
+  // sorted row holds them at its start.
   std::vector<int32_t> perm((size_t)n), inv((size_t)n);
   {
-    std::vector<int64_t> at((size_t)maxdeg + 2, 0);
-    for (int32_t v = 0; v < n; v++) at[(size_t)(maxdeg - deg[v]) + 1]++;
-    for (size_t b = 1; b < at.size(); b++) at[b] += at[b - 1];
-    for (int32_t v = 0; v < n; v++) {
-      const int64_t pos = at[(size_t)(maxdeg - deg[v])]++;
-      perm[(size_t)pos] = v;
-      inv[(size_t)v] = (int32_t)pos;
+    std::vector<uint64_t> w0((size_t)n);
+    for (int32_t v = 0; v < n; v++) w0[(size_t)v] = (uint64_t)deg[(size_t)v];
+    if (d->metric != KWS_DSD_DG) {
+      std::fill(w0.begin(), w0.end(), 0ull);
+      for (int64_t e = 0; e < m; e++) {
+        const int32_t u = d->src[e], v = d->dst[e];
+        const uint64_t c = d->metric == KWS_DSD_DW ? (uint64_t)d->edge_w[e] : (uint64_t)fd_table[(size_t)deg[(size_t)u]];
+        w0[(size_t)u] += c;
+        w0[(size_t)v] += c;
+      }
+      if (d->metric == KWS_DSD_FD)
+        for (int32_t v = 0; v < n; v++) w0[(size_t)v] += (uint64_t)d->vertex_w[v];
     }
+    // stable LSD radix sort of the ids by ~w0 (descending w0, ties by id)
+    uint64_t top = 0;
+    for (int32_t v = 0; v < n; v++) top = std::max(top, w0[(size_t)v]);
+    std::vector<int32_t> tmp((size_t)n);
+    for (int32_t v = 0; v < n; v++) perm[(size_t)v] = v;
+    for (int shift = 0; shift < 64 && (top >> shift) != 0; shift += 16) {
+      std::vector<int64_t> at(65537, 0);
+      for (int32_t i = 0; i < n; i++) at[(((top - w0[(size_t)perm[(size_t)i]]) >> shift) & 0xffff) + 1]++;
+      for (size_t b = 1; b < at.size(); b++) at[b] += at[b - 1];
+      for (int32_t i = 0; i < n; i++) {
+        const int32_t v = perm[(size_t)i];
+        tmp[(size_t)at[((top - w0[(size_t)v]) >> shift) & 0xffff]++] = v;
+      }
+      perm.swap(tmp);
+    }
+    for (int32_t i = 0; i < n; i++) inv[(size_t)perm[(size_t)i]] = i;
   }
   std::vector<int32_t> ideg((size_t)n);
   std::vector<int64_t> ptr((size_t)n + 1, 0);
