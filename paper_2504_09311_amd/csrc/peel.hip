@@ -2,21 +2,21 @@
 // Algorithm 2), with the DG, DW and FD weight functions of Section 2.1.
 //
 // Layout: vertices are renumbered at load by descending initial peeling
-// weight (ties by id), so the survivors of the later rounds, the dense part, hold the
-// smallest ids; every edge is stored twice in an incidence CSR (once in the
-// row of each endpoint, rows sorted by neighbour id) with its weight and a
-// running sum of the weights; per vertex the current peeling weight w
-// (int64), the round it was peeled in (in the caller's ids) and an alive
-// bit (the bitmap is n/8 bytes, so random alive tests hit L2), and two
-// ping-pong lists of the vertices still alive. Decide also records one
-// more than the largest surviving id: neighbours at or above it are gone
-// without a test, and when the survivors are exactly the ids below it the
-// bitmap is not read at all. A step is four launches
+// weight (ties by id), so the first round's survivors are the smallest ids
+// and the later rounds' survivors, the dense part, stay among them; every
+// edge is stored twice in an incidence CSR (once in the row of each
+// endpoint, rows sorted by neighbour id) with its weight and a running sum
+// of the weights; per vertex the current peeling weight w (int64), the
+// round it was peeled in (copied out in the caller's ids at the end of a
+// run) and an alive bit (the bitmap is n/8 bytes, so random alive tests
+// hit L2), and two ping-pong lists of the vertices still alive. Decide also
+// records one more than the largest surviving id: neighbours at or above
+// it are gone without a test, and when the survivors are exactly the ids
+// below it the bitmap is not read at all. A step is four kinds of launch
 // (plus one thread that picks its kind), all on the device:
 //   decide  scan the alive list: w_u * |S| * den <= k * (den + num) * f
 //           (128-bit products) puts u on the peeled list, else on the next
-//           alive list (and its row, in pieces, on the pull list); appends
-//           are aggregated per block;
+//           alive list; appends are aggregated per block;
 //   update  push: the peeled vertices subtract their edge weights from the
 //           neighbours still alive (64-bit atomics); or pull: the survivors
 //           re-sum their alive neighbours (a binary search per survivor,
@@ -25,7 +25,7 @@
 //           per alive neighbour (chosen on the device);
 //   reduce  sum of a + w over the survivors (= 2 f(S_i));
 //   end     one thread: f, |S|, the per-round record and the densest S_i.
-// The host only enqueues rounds and reads |S| every few rounds to stop.
+// The host only enqueues steps and reads |S| every few steps to stop.
 // Everything is integer arithmetic, so results do not depend on the order
 // of the atomics.
 #include <hip/hip_runtime.h>
@@ -126,11 +126,11 @@ __global__ __launch_bounds__(BLOCK) void k_w0_small(int32_t n, const int64_t *__
 
 // start of a run: S_0 = V
 __global__ __launch_bounds__(BLOCK) void k_start(int32_t n, const int64_t *__restrict__ w0, int64_t *__restrict__ w,
-                                                 int32_t *__restrict__ rnd, int32_t *__restrict__ list,
+                                                 int32_t *__restrict__ rnd_in, int32_t *__restrict__ list,
                                                  uint32_t *__restrict__ alive) {
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
     w[v] = w0[v];
-    rnd[v] = ALIVE;
+    rnd_in[v] = ALIVE;
     list[v] = (int32_t)v;
     if ((v & 31) == 0) alive[v >> 5] = n - v >= 32 ? ~0u : (1u << (n - v)) - 1u;
   }
@@ -288,8 +288,8 @@ constexpr int PER = 8, CHUNK = PER * BLOCK;
 __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la, int ca,
                                                   int32_t *__restrict__ lb, int cb, int32_t *__restrict__ ul,
                                                   int32_t n_total, PeelScalars *sc, const int64_t *__restrict__ w,
-                                                  const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd,
-                                                  const int32_t *__restrict__ perm, uint32_t *__restrict__ alive,
+                                                  const int64_t *__restrict__ ptr, int32_t *__restrict__ rnd_in,
+                                                  uint32_t *__restrict__ alive,
                                                   int32_t k, int32_t num, int32_t den) {
   __shared__ unsigned s_w[BLOCK / 64];
   __shared__ unsigned long long s_base[3];
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
       clear_alive(alive, v[j], (peel_bits >> j) & 1u);
       if (v[j] < 0) continue;
       if ((peel_bits >> j) & 1u) {
-        rnd[perm[v[j]]] = round;   // rounds are kept in the caller's ids
+        rnd_in[v[j]] = round;
         if ((big_bits >> j) & 1u) ul[n_total - 1 - pb++] = v[j];   // large rows fill the list from its end
         else ul[pu++] = v[j];
       } else {
@@ -575,6 +575,14 @@ __global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int3
   sc->cnt[1 - cl] = 0;
 }
 
+// end of a run: the peel rounds in the caller's ids (a gather through the
+// id map, so the stores are coalesced)
+__global__ __launch_bounds__(BLOCK) void k_export(int32_t n, const int32_t *__restrict__ inv,
+                                                  const int32_t *__restrict__ rnd_in, int32_t *__restrict__ rnd) {
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
+    rnd[v] = rnd_in[inv[v]];
+}
+
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, cap));
 }
@@ -596,7 +604,8 @@ struct kws_dsd_graph {
   int64_t *w0 = nullptr;           // [n] peeling weights in G (start of every run)
   int64_t *w = nullptr;            // [n] peeling weights
   int32_t *rnd = nullptr;          // [n] round of removal, in the caller's ids
-  int32_t *perm = nullptr;         // [n] caller's id of each internal id
+  int32_t *rnd_in = nullptr;       // [n] round of removal, in internal ids
+  int32_t *inv = nullptr;          // [n] internal id of each caller's id
   int32_t *list[2] = {nullptr, nullptr};
   int32_t *ul = nullptr;           // [n] peeled in the current round
   uint32_t *alive = nullptr;       // [(n + 31) / 32] alive bits
@@ -613,7 +622,7 @@ namespace {
 void dsd_release(kws_dsd_graph *g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
-  void *ps[] = {g->ptr, g->nbr, g->wt, g->wcum, g->a, g->big, g->w0, g->w, g->rnd, g->perm, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sc,
+  void *ps[] = {g->ptr, g->nbr, g->wt, g->wcum, g->a, g->big, g->w0, g->w, g->rnd, g->rnd_in, g->inv, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sc,
                 g->d_sizes, g->d_f};
   for (void *p : ps) kws::dev_free(p);
   if (g->stream) (void)hipStreamDestroy(g->stream);
@@ -769,12 +778,12 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
     return bail(fail(KWS_EDEVICE, "stream creation failed"));
   hipStream_t s = g->stream;
   kws_status st = KWS_OK;
-  int32_t *d_src = nullptr, *d_dst = nullptr, *d_deg = nullptr, *d_inv = nullptr;
+  int32_t *d_src = nullptr, *d_dst = nullptr, *d_deg = nullptr;
   int64_t *d_ew = nullptr, *d_fd = nullptr, *d_vals = nullptr;
   unsigned long long *d_keys = nullptr, *d_sorted = nullptr;
   void *d_tmp = nullptr;
   auto cleanup = [&]() {
-    dev_free(d_src); dev_free(d_dst); dev_free(d_deg); dev_free(d_inv); dev_free(d_ew); dev_free(d_fd);
+    dev_free(d_src); dev_free(d_dst); dev_free(d_deg); dev_free(d_ew); dev_free(d_fd);
     dev_free(d_vals); dev_free(d_keys); dev_free(d_sorted); dev_free(d_tmp);
   };
 #define DSD_STEP(x) do { st = (x); if (st != KWS_OK) { cleanup(); return bail(st); } } while (0)
@@ -787,7 +796,8 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   DSD_STEP(dev_array(&g->w0, (size_t)n, "initial peeling weights"));
   DSD_STEP(dev_array(&g->w, (size_t)n, "peeling weights"));
   DSD_STEP(dev_array(&g->rnd, (size_t)n, "peel rounds"));
-  DSD_STEP(dev_array(&g->perm, (size_t)n, "id map"));
+  DSD_STEP(dev_array(&g->rnd_in, (size_t)n, "peel rounds (internal ids)"));
+  DSD_STEP(dev_array(&g->inv, (size_t)n, "id map"));
   DSD_STEP(dev_array(&g->list[0], (size_t)n, "alive list"));
   DSD_STEP(dev_array(&g->list[1], (size_t)n, "alive list"));
   DSD_STEP(dev_array(&g->ul, (size_t)n, "peeled list"));
@@ -796,19 +806,17 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   DSD_STEP(dev_array(&g->sc, 1, "peeling scalars"));
   g->nbig = (int32_t)big.size();
   DSD_HIP(hipMemcpyAsync(g->ptr, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
-  if (n > 0) DSD_HIP(hipMemcpyAsync(g->perm, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  if (n > 0) DSD_HIP(hipMemcpyAsync(g->inv, inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
   if (!big.empty()) DSD_HIP(hipMemcpyAsync(g->big, big.data(), sizeof(int32_t) * big.size(), hipMemcpyHostToDevice, s));
   if (g->a) DSD_HIP(hipMemcpyAsync(g->a, ia.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, s));
   if (m > 0) {
     const size_t inc = (size_t)(2 * m);
     DSD_STEP(dev_array(&d_src, (size_t)m, "edge sources"));
     DSD_STEP(dev_array(&d_dst, (size_t)m, "edge targets"));
-    DSD_STEP(dev_array(&d_inv, (size_t)n, "id map"));
     DSD_STEP(dev_array(&d_keys, inc, "incidence keys"));
     DSD_STEP(dev_array(&d_sorted, inc, "sorted incidence keys"));
     DSD_HIP(hipMemcpyAsync(d_src, d->src, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
     DSD_HIP(hipMemcpyAsync(d_dst, d->dst, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
-    DSD_HIP(hipMemcpyAsync(d_inv, inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     if (d->metric == KWS_DSD_DW) {
       DSD_STEP(dev_array(&d_ew, (size_t)m, "edge weights"));
       DSD_HIP(hipMemcpyAsync(d_ew, d->edge_w, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, s));
@@ -820,7 +828,7 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
       DSD_HIP(hipMemcpyAsync(d_deg, ideg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
     }
     if (g->wt) DSD_STEP(dev_array(&d_vals, inc, "incidence weight keys"));
-    k_keys<<<grid_for(m, BLOCK, 65536), BLOCK, 0, s>>>(d_src, d_dst, d_ew, m, d->metric, d_fd, d_deg, d_inv, d_keys,
+    k_keys<<<grid_for(m, BLOCK, 65536), BLOCK, 0, s>>>(d_src, d_dst, d_ew, m, d->metric, d_fd, d_deg, g->inv, d_keys,
                                                        d_vals);
     DSD_HIP(hipGetLastError());
     // sort by (row, neighbour): 32 bits of neighbour and the bits of a row id
@@ -902,7 +910,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   KWS_HIP(hipGetLastError());
   g->has_run = false;
   k_scalars_init<<<1, 64, 0, s>>>(g->sc, n);
-  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd, g->list[0], g->alive);
+  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd_in, g->list[0], g->alive);
   {
     DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
     k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
@@ -924,7 +932,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     {
       DsdTimer t(t_dec, DSD_DECIDE, s, &evlog);
       k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
-                                                                   g->w, g->ptr, g->rnd, g->perm, g->alive, p->k,
+                                                                   g->w, g->ptr, g->rnd_in, g->alive, p->k,
                                                                    p->eps_num, p->eps_den);
     }
     {
@@ -950,6 +958,8 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
       if (h.round + 1 >= g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
     }
   }
+  k_export<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->inv, g->rnd_in, g->rnd);
+  KWS_HIP(hipGetLastError());
   PeelScalars h;
   KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
   KWS_HIP(hipStreamSynchronize(s));
