@@ -256,9 +256,11 @@ def peel_bench(args):
             bytes_ = peel_bytes(metric, n, sizes_p, smp)
             kern = {k: dict(launches=int(smp[k + "_launches"]), total_ms=round(smp[k + "_ms"], 4),
                             avg_us=round(smp[k + "_ms"] * 1e3 / max(1, smp[k + "_launches"]), 3)) for k in bytes_}
-            # the roofline kernel: k_decide, the largest single kernel of a
-            # run (update is a class of four launches, of which the paths not
-            # taken return at once, so its event time is mostly launch gaps)
+            # the roofline kernel: k_decide, which runs once per step over
+            # the whole alive set and is, with the pull reset's binary
+            # searches, the largest single kernel of a run (update is a class
+            # of four launches, of which the paths not taken return at once,
+            # so its event time holds their launch gaps)
             dom = "decide"
             # timed runs; for the lead configuration the dominant class is
             # bracketed by events (read after each run) for the roofline
