@@ -59,6 +59,10 @@ typedef struct kws_dsd_graph kws_dsd_graph;
  *   edge_w[m]       DW edge weights (>= 0, sum below 2^55); NULL for DG and FD
  *   vertex_w[n]     FD vertex weights (>= 0, 2^-24 units); NULL for DG and DW
  *   metric          KWS_DSD_DG, KWS_DSD_DW or KWS_DSD_FD
+ * Device memory held by the graph: 4 B per edge endpoint (2m endpoints;
+ * DW and FD add 16 B: the weight and a running sum) and about 60 B per
+ * vertex; the load itself also takes 16 B per endpoint (32 B for DW and FD)
+ * for the sort that orders the rows, freed before it returns.
  * KWS_EINVAL on a malformed graph (nothing is allocated then), KWS_ENOMEM
  * if the device copies do not fit. */
 typedef struct {
@@ -92,7 +96,7 @@ typedef struct {
   int32_t best;          /* index of the densest S_i */
   int64_t best_size;     /* |S_best| */
   int64_t best_f;        /* f(S_best) */
-  int64_t incidences;    /* edge endpoints processed by the neighbour updates */
+  int64_t incidences;    /* edge endpoints of the graph (2m) */
   double decide_ms, update_ms, reduce_ms;   /* summed kernel time (profile = 1) */
   int64_t decide_launches, update_launches, reduce_launches;
   int64_t trims;         /* trimming steps (LPO) */
