@@ -228,8 +228,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_lt(const int32_t *__restrict__ 
 // survivor of the round is lighter than g(S); otherwise the round is over:
 // its set is a candidate for the densest, and the next round starts with
 // tau_max refined (GPO, LPO) from g of that set.
-__global__ void k_phase(PeelScalars *sc, int32_t mode, int32_t k, int32_t num, int32_t den) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void next_phase(PeelScalars *sc, int32_t mode, int32_t k, int32_t num, int32_t den) {
   const long long f = sc->f, s = sc->s;
   if (s == 0) { sc->phase = STEP_DONE; return; }
   if (mode == MODE_LPO && sc->round > 0 && sc->nlt > 0) {
@@ -256,6 +255,10 @@ __global__ void k_phase(PeelScalars *sc, int32_t mode, int32_t k, int32_t num, i
   }
   sc->round++;
   sc->phase = STEP_PEEL;
+}
+
+__global__ void k_phase(PeelScalars *sc, int32_t mode, int32_t k, int32_t num, int32_t den) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) next_phase(sc, mode, k, num, den);
 }
 
 // exclusive prefix sum over the block of one value per thread
@@ -388,12 +391,10 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
 // every survivor's row in pieces of PIECE incidences (a row of many pieces
 // is listed by the whole wavefront); reserved once per block and chunk
 constexpr int IPER = 4, ICHUNK = IPER * BLOCK;
-__global__ __launch_bounds__(BLOCK) void k_items(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
-                                                 const int64_t *__restrict__ ptr,
-                                                 unsigned long long *__restrict__ items) {
+__device__ __forceinline__ void list_items(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+                                           const int64_t *__restrict__ ptr, unsigned long long *__restrict__ items) {
   __shared__ unsigned s_w[BLOCK / 64];
   __shared__ unsigned long long s_base;
-  if (!pull_step(sc, cb) || prefix_alive(sc, cb)) return;
   const unsigned long long count = sc->cnt[cb];
   for (unsigned long long c0 = (unsigned long long)blockIdx.x * ICHUNK; c0 < count;
        c0 += (unsigned long long)gridDim.x * ICHUNK) {
@@ -435,12 +436,10 @@ __global__ __launch_bounds__(BLOCK) void k_items(const int32_t *__restrict__ lb,
 // neighbours still alive; a thread per vertex with a small row, a
 // wavefront per vertex with a large one. Runs while the removed vertices
 // have few incidences next to the survivors' (pull_step).
-__global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict__ ul, int32_t n_total,
-                                                       PeelScalars *sc, int cb, const int64_t *__restrict__ ptr,
-                                                       const int32_t *__restrict__ nbr,
-                                                       const int64_t *__restrict__ wt,
-                                                       const uint32_t *__restrict__ alive, int64_t *__restrict__ w) {
-  if (pull_step(sc, cb)) return;
+__device__ __forceinline__ void push_updates(const int32_t *__restrict__ ul, int32_t n_total, PeelScalars *sc, int cb,
+                                             const int64_t *__restrict__ ptr, const int32_t *__restrict__ nbr,
+                                             const int64_t *__restrict__ wt, const uint32_t *__restrict__ alive,
+                                             int64_t *__restrict__ w) {
   const unsigned long long nu = sc->nu, nb = sc->nu_big;
   const int32_t bound = sc->bound;
   const bool prefix = prefix_alive(sc, cb);
@@ -474,13 +473,10 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(const int32_t *__restrict
 // survivor's row (listed by decide) is summed over the alive neighbours by
 // one wavefront and added with one atomic, so hub rows spread over many
 // wavefronts.
-__global__ __launch_bounds__(BLOCK) void k_update_pull_reset(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
-                                                             const int64_t *__restrict__ a,
-                                                             const int64_t *__restrict__ ptr,
-                                                             const int32_t *__restrict__ nbr,
-                                                             const int64_t *__restrict__ wcum,
-                                                             int64_t *__restrict__ w) {
-  if (!pull_step(sc, cb)) return;
+__device__ __forceinline__ void pull_reset(const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+                                           const int64_t *__restrict__ a, const int64_t *__restrict__ ptr,
+                                           const int32_t *__restrict__ nbr, const int64_t *__restrict__ wcum,
+                                           int64_t *__restrict__ w) {
   const unsigned long long count = sc->cnt[cb];
   const bool prefix = prefix_alive(sc, cb);
   const int32_t bound = sc->bound;
@@ -502,6 +498,23 @@ __global__ __launch_bounds__(BLOCK) void k_update_pull_reset(const int32_t *__re
     }
     w[v] = x;
   }
+}
+
+// the first launch of the update: push, or the pull's reset (and its work
+// list when the survivors are not the ids below the bound); the role is the
+// same for the whole grid
+__global__ __launch_bounds__(BLOCK) void k_update(const int32_t *__restrict__ ul, int32_t n_total,
+                                                  const int32_t *__restrict__ lb, int cb, PeelScalars *sc,
+                                                  const int64_t *__restrict__ a, const int64_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ nbr, const int64_t *__restrict__ wt,
+                                                  const int64_t *__restrict__ wcum, const uint32_t *__restrict__ alive,
+                                                  unsigned long long *__restrict__ items, int64_t *__restrict__ w) {
+  if (!pull_step(sc, cb)) {
+    push_updates(ul, n_total, sc, cb, ptr, nbr, wt, alive, w);
+    return;
+  }
+  if (!prefix_alive(sc, cb)) list_items(lb, cb, sc, ptr, items);
+  pull_reset(lb, cb, sc, a, ptr, nbr, wcum, w);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_update_pull(const unsigned long long *__restrict__ items, PeelScalars *sc,
@@ -559,7 +572,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(const int32_t *__restrict__ li
 // close a step: survivors are in list cl; the next step fills 1 - cl. The
 // record of the round is rewritten by every step of it (the last, after
 // trimming, stays).
-__global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int32_t cap) {
+__global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int32_t cap, int32_t mode, int32_t k,
+                      int32_t num, int32_t den) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (sc->phase == STEP_DONE) return;
   const int32_t round = sc->round;
@@ -573,6 +587,9 @@ __global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int3
   sc->nitems = 0;
   sc->bound = 0;
   sc->cnt[1 - cl] = 0;
+  // without trimming the next step's kind needs nothing more: pick it here
+  // (with trimming, the count of light survivors comes first)
+  if (mode != MODE_LPO) next_phase(sc, mode, k, num, den);
 }
 
 // end of a run: the peel rounds in the caller's ids (a gather through the
@@ -915,7 +932,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
     k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
   }
-  k_end<<<1, 64, 0, s>>>(0, g->sc, g->d_sizes, g->d_f, g->d_cap);
+  k_end<<<1, 64, 0, s>>>(0, g->sc, g->d_sizes, g->d_f, g->d_cap, p->mode, p->k, p->eps_num, p->eps_den);
   KWS_HIP(hipGetLastError());
   // Steps are enqueued without waiting: the device decides whether a step
   // peels (a new round), trims (LPO) or, once the set is empty, does
@@ -926,9 +943,10 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     if (step > (int64_t)n + 1) return fail(KWS_EDEVICE, "peeling did not finish in %d steps", n + 1);
     step++;
     const int ca = (int)((step - 1) & 1), cb = (int)(step & 1);
-    if (p->mode == KWS_DSD_LPO)
+    if (p->mode == KWS_DSD_LPO) {   // otherwise k_end has picked the step's kind
       k_count_lt<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->sc, g->w);
-    k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
+      k_phase<<<1, 64, 0, s>>>(g->sc, p->mode, p->k, p->eps_num, p->eps_den);
+    }
     {
       DsdTimer t(t_dec, DSD_DECIDE, s, &evlog);
       k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
@@ -937,18 +955,15 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     }
     {
       DsdTimer t(t_upd, DSD_UPDATE, s, &evlog);
-      k_items<<<grid_for(known, ICHUNK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->ptr, g->items);
-      k_update_push<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->sc, cb, g->ptr, g->nbr,
-                                                                            g->wt, g->alive, g->w);
-      k_update_pull_reset<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->ptr,
-                                                                             g->nbr, g->wcum, g->w);
+      k_update<<<grid_for(known * 64, BLOCK, resident), BLOCK, 0, s>>>(g->ul, n, g->list[cb], cb, g->sc, g->a, g->ptr,
+                                                                       g->nbr, g->wt, g->wcum, g->alive, g->items, g->w);
       k_update_pull<<<(unsigned)resident, BLOCK, 0, s>>>(g->items, g->sc, cb, g->ptr, g->nbr, g->wt, g->alive, g->w);
     }
     {
       DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
       k_reduce<<<grid_for(known, BLOCK, resident), BLOCK, 0, s>>>(g->list[cb], cb, g->sc, g->a, g->w);
     }
-    k_end<<<1, 64, 0, s>>>(cb, g->sc, g->d_sizes, g->d_f, g->d_cap);
+    k_end<<<1, 64, 0, s>>>(cb, g->sc, g->d_sizes, g->d_f, g->d_cap, p->mode, p->k, p->eps_num, p->eps_den);
     KWS_HIP(hipGetLastError());
     if (step % 4 == 0 || known < 4096) {
       PeelScalars h;
