@@ -196,19 +196,20 @@ PEEL_METRIC = "densest-subgraph parallel peeling (eps=0.1): edges per second ove
 
 def peel_bytes(metric: str, n: int, sizes, summary) -> dict:
     """Algorithmic bytes of one run per kernel class, counted per peeling
-    round. decide reads an alive vertex's list entry, weight and row
-    offsets and writes it to one list (32 B), plus the round of a removed
+    round. decide reads an alive vertex's list entry (not in the first
+    step, whose list is the identity), weight and row offsets and writes it
+    to one list (32 B, 28 B in the first step), plus the round of a removed
     vertex (4 B); update writes every survivor's new weight from its list
     entry and row offsets (28 B, FD 36 B with the vertex weight); the
     incidences it reads depend on the path (a binary search per survivor,
     or a pass over the survivors' rows) and are not counted; reduce reads
-    list entry, weight and vertex weight (FD) of every survivor (12 or 20 B).
-    A trimming step of local trimming is not in the rounds record."""
+    list entry, weight and vertex weight (FD) of every survivor (12 or 20
+    B). A trimming step of local trimming is not in the rounds record."""
     alive_before = int(sum(sizes[:-1]))
     survivors = int(sum(sizes[1:]))
-    return dict(decide=32.0 * alive_before + 4.0 * n,
+    return dict(decide=32.0 * alive_before - 4.0 * int(sizes[0]) + 4.0 * n,
                 update=(36.0 if metric == "FD" else 28.0) * survivors,
-                reduce=(20.0 if metric == "FD" else 12.0) * (survivors + n))
+                reduce=(20.0 if metric == "FD" else 12.0) * survivors)
 
 
 def copy_probe(mb: int):

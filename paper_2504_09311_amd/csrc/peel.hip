@@ -124,14 +124,13 @@ __global__ __launch_bounds__(BLOCK) void k_w0_small(int32_t n, const int64_t *__
   }
 }
 
-// start of a run: S_0 = V
+// start of a run: S_0 = V (the first step reads its alive list as the
+// identity, so none is written)
 __global__ __launch_bounds__(BLOCK) void k_start(int32_t n, const int64_t *__restrict__ w0, int64_t *__restrict__ w,
-                                                 int32_t *__restrict__ rnd_in, int32_t *__restrict__ list,
-                                                 uint32_t *__restrict__ alive) {
+                                                 int32_t *__restrict__ rnd_in, uint32_t *__restrict__ alive) {
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
     w[v] = w0[v];
     rnd_in[v] = ALIVE;
-    list[v] = (int32_t)v;
     if ((v & 31) == 0) alive[v >> 5] = n - v >= 32 ? ~0u : (1u << (n - v)) - 1u;
   }
 }
@@ -150,11 +149,29 @@ __global__ __launch_bounds__(BLOCK) void k_w0_big(const int32_t *__restrict__ bi
   }
 }
 
-__global__ void k_scalars_init(PeelScalars *sc, int32_t n) {
+// 2 f(V) = sum of a + w over V, once at load
+__global__ __launch_bounds__(BLOCK) void k_sum_all(int32_t n, const int64_t *__restrict__ a,
+                                                   const int64_t *__restrict__ w0, unsigned long long *out) {
+  __shared__ unsigned long long s_part[BLOCK / 64];
+  unsigned long long t = 0;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
+    t += (unsigned long long)w0[v] + (a ? (unsigned long long)a[v] : 0ull);
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long u = 0;
+    for (int i = 0; i < BLOCK / 64; i++) u += s_part[i];
+    if (u) atomicAdd(out, u);
+  }
+}
+
+__global__ void k_scalars_init(PeelScalars *sc, int32_t n, const unsigned long long *sum_all) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->cnt[0] = (unsigned long long)n;
     sc->cnt[1] = 0;
-    sc->nu = sc->nu_big = sc->sum2 = sc->deg_peel = sc->deg_keep = sc->nlt = sc->trims = sc->nitems = 0;
+    sc->nu = sc->nu_big = sc->deg_peel = sc->deg_keep = sc->nlt = sc->trims = sc->nitems = 0;
+    sc->sum2 = *sum_all;                // the reduce of S_0 = V
     sc->tau_lo = sc->tau_hi = 0;
     sc->tau_den = 1;
     sc->f = sc->s = sc->best_f = 0;
@@ -318,7 +335,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(const int32_t *__restrict__ la
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       const unsigned long long idx = c0 + (unsigned long long)j * BLOCK + threadIdx.x;
-      v[j] = idx < count ? la[idx] : -1;
+      v[j] = idx < count ? (la ? la[idx] : (int32_t)idx) : -1;   // no list: the identity (first step)
     }
 #pragma unroll
     for (int j = 0; j < PER; j++) {
@@ -619,6 +636,7 @@ struct kws_dsd_graph {
   int32_t *big = nullptr;          // vertices whose row is summed by a wavefront
   int32_t nbig = 0;
   int64_t *w0 = nullptr;           // [n] peeling weights in G (start of every run)
+  unsigned long long *sum_all = nullptr;   // 2 f(V)
   int64_t *w = nullptr;            // [n] peeling weights
   int32_t *rnd = nullptr;          // [n] round of removal, in the caller's ids
   int32_t *rnd_in = nullptr;       // [n] round of removal, in internal ids
@@ -639,7 +657,7 @@ namespace {
 void dsd_release(kws_dsd_graph *g) {
   if (!g) return;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
-  void *ps[] = {g->ptr, g->nbr, g->wt, g->wcum, g->a, g->big, g->w0, g->w, g->rnd, g->rnd_in, g->inv, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sc,
+  void *ps[] = {g->ptr, g->nbr, g->wt, g->wcum, g->a, g->big, g->w0, g->w, g->rnd, g->rnd_in, g->inv, g->list[0], g->list[1], g->ul, g->alive, g->items, g->sum_all, g->sc,
                 g->d_sizes, g->d_f};
   for (void *p : ps) kws::dev_free(p);
   if (g->stream) (void)hipStreamDestroy(g->stream);
@@ -821,6 +839,7 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   DSD_STEP(dev_array(&g->alive, ((size_t)n + 31) / 32, "alive bits"));
   DSD_STEP(dev_array(&g->items, (size_t)n + (size_t)(2 * m) / PIECE + 1, "pull items"));
   DSD_STEP(dev_array(&g->sc, 1, "peeling scalars"));
+  DSD_STEP(dev_array(&g->sum_all, 1, "2 f(V)"));
   g->nbig = (int32_t)big.size();
   DSD_HIP(hipMemcpyAsync(g->ptr, ptr.data(), sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
   if (n > 0) DSD_HIP(hipMemcpyAsync(g->inv, inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
@@ -881,6 +900,8 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out) {
   k_w0_small<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->ptr, g->wt, g->a, g->w0);
   if (g->nbig && g->wt)
     k_w0_big<<<grid_for((int64_t)g->nbig * 64, BLOCK, 65536), BLOCK, 0, s>>>(g->big, g->nbig, g->ptr, g->wt, g->w0);
+  DSD_HIP(hipMemsetAsync(g->sum_all, 0, sizeof(unsigned long long), s));
+  k_sum_all<<<grid_for(n, BLOCK, 2048), BLOCK, 0, s>>>(n, g->a, g->w0, g->sum_all);
   DSD_HIP(hipGetLastError());
   DSD_HIP(hipStreamSynchronize(s));
   cleanup();
@@ -926,12 +947,8 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   const int64_t resident = 2048;
   KWS_HIP(hipGetLastError());
   g->has_run = false;
-  k_scalars_init<<<1, 64, 0, s>>>(g->sc, n);
-  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd_in, g->list[0], g->alive);
-  {
-    DsdTimer t(t_red, DSD_REDUCE, s, &evlog);
-    k_reduce<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(g->list[0], 0, g->sc, g->a, g->w);
-  }
+  k_scalars_init<<<1, 64, 0, s>>>(g->sc, n, g->sum_all);
+  k_start<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->w0, g->w, g->rnd_in, g->alive);
   k_end<<<1, 64, 0, s>>>(0, g->sc, g->d_sizes, g->d_f, g->d_cap, p->mode, p->k, p->eps_num, p->eps_den);
   KWS_HIP(hipGetLastError());
   // Steps are enqueued without waiting: the device decides whether a step
@@ -949,7 +966,8 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
     }
     {
       DsdTimer t(t_dec, DSD_DECIDE, s, &evlog);
-      k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(g->list[ca], ca, g->list[cb], cb, g->ul, n, g->sc,
+      k_decide<<<grid_for(known, CHUNK, resident), BLOCK, 0, s>>>(step == 1 ? nullptr : g->list[ca], ca, g->list[cb],
+                                                                   cb, g->ul, n, g->sc,
                                                                    g->w, g->ptr, g->rnd_in, g->alive, p->k,
                                                                    p->eps_num, p->eps_den);
     }
