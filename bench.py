@@ -298,9 +298,10 @@ def peel_bench(args):
     cpu = None
     if args.cpu_budget > 0 and metrics[0] == "DG":
         import oracle
-        # the oracle recomputes every sum in every round; a bounded sample is
-        # the same recipe at 2^20 vertices when the input is larger
-        sample = inp if m <= (1 << 25) else W.peel_input("peel_rmat20")
+        # the oracle recomputes every sum in every round: the whole input up
+        # to 2^29 edges (R-MAT 2^24, 263 M edges: ~20 s on one core), else the
+        # same recipe at 2^20 vertices
+        sample = inp if m <= (1 << 29) else W.peel_input("peel_rmat20")
         c, a = oracle.metric_weights("DG", sample["src"], sample["dst"], sample["n"])
         t0 = time.perf_counter()
         oracle.peel(sample["n"], sample["src"], sample["dst"], c, a, 2, 1, 10, cap=4096)
