@@ -679,7 +679,7 @@ struct DsdEvents {
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
   ~DsdEvents() {
-    for (Rec &r : recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+    for (Rec &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   }
   void collect(kws_dsd_summary &sum) {
     double *ms[3] = {&sum.decide_ms, &sum.update_ms, &sum.reduce_ms};
@@ -699,14 +699,14 @@ struct DsdTimer {
   DsdTimer(bool on, int cls_, hipStream_t s_, DsdEvents *log_) : log(nullptr), cls(cls_), s(s_) {
     if (on && hipEventCreate(&a) == hipSuccess) {
       log = log_;
-      hipEventRecord(a, s);
+      (void)hipEventRecord(a, s);   // a failed record makes this pair's elapsed time fail: it is skipped
     }
   }
   ~DsdTimer() {
     if (!log) return;
     hipEvent_t b = nullptr;
-    if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); return; }
-    hipEventRecord(b, s);
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    (void)hipEventRecord(b, s);
     log->recs.push_back({cls, a, b});
   }
 };
