@@ -49,6 +49,7 @@ constexpr int SMALL_DEG = 64;   // rows above this are summed by a wavefront at 
 constexpr int SMALL_PUSH = 16;  // peeled rows up to this are pushed by one thread
 constexpr int PIECE = 1024;     // incidences of a survivor's row summed by one wavefront (pull)
 constexpr uint32_t FEW_PIECES = 4;   // rows of more pieces are listed by the whole wavefront
+constexpr int MAX_CUTS = 64;          // steps whose survivor bounds are kept for the export
 // push costs an atomic per alive neighbour, pull streams ids and tests a bit:
 // push is taken while the removed vertices have at most 1/PUSH_COST of the
 // survivors' incidences
@@ -79,6 +80,10 @@ struct PeelScalars {
   long long f, s;              // f(S), |S| of the current set
   long long best_f, best_s;
   int best_i, round, phase;
+  // the survivors after step i were the ids below cut[i] (i < MAX_CUTS),
+  // as long as every step so far left such a prefix (not nonprefix)
+  int ncut, nonprefix;
+  int cut[MAX_CUTS], cut_round[MAX_CUTS];
 };
 
 // incidence keys of the relabelled graph, (row << 32) | neighbour, one
@@ -180,6 +185,8 @@ __global__ void k_scalars_init(PeelScalars *sc, int32_t n, const unsigned long l
     sc->round = 0;
     sc->phase = STEP_PEEL;
     sc->bound = n;
+    sc->ncut = 0;
+    sc->nonprefix = 0;
   }
 }
 
@@ -596,6 +603,14 @@ __global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int3
   const int32_t round = sc->round;
   const long long f = (long long)(sc->sum2 / 2ull), s = (long long)sc->cnt[cl];
   if (round < cap) { sizes[round] = s; fs[round] = f; }
+  // the step removed the ids in [bound, the previous bound) when its
+  // survivors are the ids below the bound
+  if ((unsigned long long)sc->bound != sc->cnt[cl]) sc->nonprefix = 1;
+  if (sc->ncut < MAX_CUTS) {
+    sc->cut[sc->ncut] = sc->bound;
+    sc->cut_round[sc->ncut] = round;
+  }
+  sc->ncut++;
   sc->f = f;
   sc->s = s;
   sc->sum2 = 0;
@@ -609,12 +624,37 @@ __global__ void k_end(int cl, PeelScalars *sc, int64_t *sizes, int64_t *fs, int3
   if (mode != MODE_LPO) next_phase(sc, mode, k, num, den);
 }
 
-// end of a run: the peel rounds in the caller's ids (a gather through the
-// id map, so the stores are coalesced)
+// end of a run: the peel rounds in the caller's ids, with coalesced
+// stores. When every step left the ids below its bound, a vertex's round
+// follows from its internal id and the steps' bounds (the first step whose
+// bound it is not below); otherwise a gather through the id map.
 __global__ __launch_bounds__(BLOCK) void k_export(int32_t n, const int32_t *__restrict__ inv,
-                                                  const int32_t *__restrict__ rnd_in, int32_t *__restrict__ rnd) {
-  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
-    rnd[v] = rnd_in[inv[v]];
+                                                  const int32_t *__restrict__ rnd_in, const PeelScalars *sc,
+                                                  int32_t *__restrict__ rnd) {
+  __shared__ int s_cut[MAX_CUTS], s_round[MAX_CUTS];
+  const int ncut = sc->ncut;
+  const bool by_cuts = !sc->nonprefix && ncut <= MAX_CUTS;
+  if (by_cuts) {
+    for (int i = threadIdx.x; i < ncut; i += BLOCK) {
+      s_cut[i] = sc->cut[i];
+      s_round[i] = sc->cut_round[i];
+    }
+    __syncthreads();
+  }
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
+    const int32_t x = inv[v];
+    if (by_cuts) {
+      int lo = 0, hi = ncut - 1;   // the last step's bound is 0: some step's bound is not above x
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (x >= s_cut[mid]) hi = mid;
+        else lo = mid + 1;
+      }
+      rnd[v] = s_round[lo];
+    } else {
+      rnd[v] = rnd_in[x];
+    }
+  }
 }
 
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
@@ -991,7 +1031,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
       if (h.round + 1 >= g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
     }
   }
-  k_export<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->inv, g->rnd_in, g->rnd);
+  k_export<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->inv, g->rnd_in, g->sc, g->rnd);
   KWS_HIP(hipGetLastError());
   PeelScalars h;
   KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
