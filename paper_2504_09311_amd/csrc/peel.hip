@@ -1031,7 +1031,7 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
       if (h.round + 1 >= g->d_cap) return fail(KWS_EOVERFLOW, "more than %d rounds", g->d_cap - 1);
     }
   }
-  k_export<<<grid_for(n, BLOCK, 65536), BLOCK, 0, s>>>(n, g->inv, g->rnd_in, g->sc, g->rnd);
+  k_export<<<grid_for(n, BLOCK, resident), BLOCK, 0, s>>>(n, g->inv, g->rnd_in, g->sc, g->rnd);
   KWS_HIP(hipGetLastError());
   PeelScalars h;
   KWS_HIP(hipMemcpyAsync(&h, g->sc, sizeof(h), hipMemcpyDeviceToHost, s));
