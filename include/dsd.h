@@ -78,7 +78,9 @@ kws_status kws_dsd_load(const kws_dsd_desc *d, kws_dsd_graph **out);
 void kws_dsd_free(kws_dsd_graph *g);
 
 /* k: 2 for the three metrics (the factor of Theorem 4.2); eps_num in
- * 0..1000, eps_den in 1..1000; profile = 1 brackets the kernel classes of
+ * 0..1000, eps_den in 1..1000; k (1 + eps) below 2 is KWS_EINVAL (the
+ * mean peeling weight is at most 2 g, so only from 2 on is every round
+ * sure to peel a vertex); profile = 1 brackets the kernel classes of
  * profile_classes with HIP events (the summary's *_ms and launches fields;
  * the events are read once the run has finished); mode: see above. */
 enum { KWS_DSD_PLAIN = 0, KWS_DSD_GPO = 1, KWS_DSD_LPO = 2 };

@@ -225,6 +225,17 @@ typedef void *(*kws_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*kws_free_fn)(void *ptr, void *ctx);
 kws_status kws_set_allocator(kws_alloc_fn alloc, kws_free_fn free_, void *ctx);
 
+/* Device-memory cap, process-wide: every device allocation of the library
+ * that would take its bytes in use above `bytes` fails with KWS_ENOMEM
+ * (bytes < 0: no cap). Overrides the KWS_MEM_LIMIT_BYTES environment
+ * variable. A graph sizes its search-state budget from the cap when it is
+ * loaded (at most the cap minus the bytes then in use), so set the cap
+ * before kws_load_graph; a server sizes its word slots from that budget.
+ * Lowering the cap frees nothing. */
+kws_status kws_set_mem_limit(int64_t bytes);
+/* Device bytes the library holds right now (graphs, search state, servers). */
+int64_t kws_mem_in_use(void);
+
 /* Graph facts. */
 typedef struct {
   int32_t n;

@@ -60,6 +60,9 @@ int orc_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const
              int32_t k, int32_t eps_num, int32_t eps_den, int32_t *peel_round, int64_t *sizes, int64_t *fs,
              int32_t cap, int32_t *rounds, int32_t *best) {
   if (n < 0 || m < 0 || k < 1 || eps_num < 0 || eps_den < 1 || cap < 1) return -1;
+  /* progress needs k (1 + eps) >= 2: the mean peeling weight is
+     (sum a + 2 sum c) / |S| <= 2 g, so the lightest vertex is peeled */
+  if ((int64_t)k * (eps_den + eps_num) < 2 * (int64_t)eps_den) return -1;
   for (int64_t e = 0; e < m; e++)
     if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n || src[e] == dst[e] || c[e] < 0) return -1;
   for (int32_t u = 0; u < n; u++)
@@ -104,7 +107,7 @@ int orc_peel(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const
         removed++;
       }
     alive -= removed;
-    if (removed == 0) { free(w); return -1; }   /* cannot happen for eps >= 0 */
+    if (removed == 0) { free(w); return -1; }   /* cannot happen for k (1 + eps) >= 2 */
   }
   *rounds = i;
   *best = bi < 0 ? 0 : bi;
@@ -196,6 +199,7 @@ int orc_peel_opt(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, c
                  int32_t k, int32_t eps_num, int32_t eps_den, int32_t mode, int32_t *peel_round, int64_t *sizes,
                  int64_t *fs, int32_t cap, int32_t *rounds, int32_t *best, int32_t *trims) {
   if (n < 0 || m < 0 || k < 1 || eps_num < 0 || eps_den < 1 || cap < 1 || mode < 0 || mode > 2) return -1;
+  if ((int64_t)k * (eps_den + eps_num) < 2 * (int64_t)eps_den) return -1;   /* as in orc_peel */
   for (int64_t e = 0; e < m; e++)
     if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n || src[e] == dst[e] || c[e] < 0) return -1;
   for (int32_t u = 0; u < n; u++)
@@ -237,7 +241,7 @@ int orc_peel_opt(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, c
       if (le_tau || le_g) { peel_round[u] = i; removed++; }
     }
     alive -= removed;
-    if (removed == 0) { free(w); return -1; }   /* cannot happen for eps >= 0 */
+    if (removed == 0) { free(w); return -1; }   /* cannot happen for k (1 + eps) >= 2 */
     f = opt_weights(n, m, src, dst, c, a, peel_round, w);
     if (mode == 2) {
       for (;;) {

@@ -36,9 +36,11 @@ std::mutex g_mem_mu;
 std::atomic<int64_t> g_dev_bytes{0};
 int64_t g_mem_limit = -1;   // KWS_MEM_LIMIT_BYTES, -1 = unlimited
 bool g_limit_read = false;
+std::mutex g_limit_mu;                          // guards g_mem_limit and g_limit_read
 std::vector<std::pair<void *, size_t>> g_live;   // allocations and their sizes
 
 int64_t mem_limit() {
+  std::lock_guard<std::mutex> lk(g_limit_mu);
   if (!g_limit_read) {
     const char *e = getenv("KWS_MEM_LIMIT_BYTES");
     g_mem_limit = e ? atoll(e) : -1;
@@ -48,9 +50,15 @@ int64_t mem_limit() {
 }
 }  // namespace
 
+void set_mem_limit(int64_t bytes) {
+  std::lock_guard<std::mutex> lk(g_limit_mu);
+  g_mem_limit = bytes < 0 ? -1 : bytes;
+  g_limit_read = true;
+}
+
 void *dev_alloc(size_t bytes) {
-  std::lock_guard<std::mutex> lk(g_mem_mu);
   const int64_t lim = mem_limit();
+  std::lock_guard<std::mutex> lk(g_mem_mu);
   if (lim >= 0 && g_dev_bytes.load() + (int64_t)bytes > lim) return nullptr;
   void *p = nullptr;
   if (g_alloc) {
@@ -227,6 +235,14 @@ kws_status kws_set_allocator(kws_alloc_fn alloc, kws_free_fn free_, void *ctx) {
   kws::g_ctx = ctx;
   return KWS_OK;
 }
+
+kws_status kws_set_mem_limit(int64_t bytes) {
+  kws::clear_error();
+  kws::set_mem_limit(bytes);
+  return KWS_OK;
+}
+
+int64_t kws_mem_in_use(void) { return kws::dev_bytes_in_use(); }
 
 kws_status kws_load_graph(const kws_graph_desc *desc, kws_graph **out) {
   kws::clear_error();

@@ -960,6 +960,11 @@ kws_status kws_dsd_peel(kws_dsd_graph *g, const kws_dsd_params *p, int32_t *peel
   if (!g || !p) return fail(KWS_EINVAL, "null argument");
   if (p->k < 1 || p->k > 64 || p->eps_num < 0 || p->eps_num > 1000 || p->eps_den < 1 || p->eps_den > 1000)
     return fail(KWS_EINVAL, "k must be 1..64, eps_num 0..1000, eps_den 1..1000");
+  // every step must peel a vertex: the mean peeling weight is at most 2 g
+  // (each edge weighs on both endpoints), so k (1 + eps) >= 2 guarantees it
+  if ((int64_t)p->k * (p->eps_den + p->eps_num) < 2 * (int64_t)p->eps_den)
+    return fail(KWS_EINVAL, "k (1 + eps) = %d (1 + %d/%d) is below 2: a peeling round may remove nothing", p->k,
+                p->eps_num, p->eps_den);
   if (p->mode < KWS_DSD_PLAIN || p->mode > KWS_DSD_LPO) return fail(KWS_EINVAL, "unknown peeling mode %d", p->mode);
   if (p->profile_classes < 0 || p->profile_classes > 7) return fail(KWS_EINVAL, "profile_classes must be 0..7");
   if ((sizes || f) && cap < 1) return fail(KWS_EINVAL, "cap must be >= 1 with sizes or f");

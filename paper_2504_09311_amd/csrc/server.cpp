@@ -337,9 +337,10 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   if (o.max_words) words = std::min(words, o.max_words);
   if (words < 1) return kws::fail(KWS_ENOMEM, "memory budget holds no word slot (%zu bytes per slot)", per_word);
   o.max_words = words;
-  // default tile: as wide as the slots allow, up to one 128-byte line of
-  // words per vertex (a pull gather moves a whole line)
-  if (o.tile_words == 0) o.tile_words = words >= 16 ? 16 : words > 4 ? 8 : words > 2 ? 4 : words > 1 ? 2 : 1;
+  // default tile: the widest power of two the slots fill, up to one
+  // 128-byte line of words per vertex (a pull gather moves a whole line);
+  // a wider tile would pad the state past the memory budget
+  if (o.tile_words == 0) o.tile_words = words >= 16 ? 16 : words >= 8 ? 8 : words >= 4 ? 4 : words >= 2 ? 2 : 1;
   // whole tiles only, within the budget (a tile wider than the slots is the
   // caller's explicit choice)
   if (words >= o.tile_words) words = words / o.tile_words * o.tile_words;

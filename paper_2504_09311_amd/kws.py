@@ -155,6 +155,8 @@ def load_library(path: str = LIB_PATH):
         "kws_set_stream": (C.c_int, [P, P]),
         "kws_get_stream": (P, [P]),
         "kws_set_allocator": (C.c_int, [P, P, P]),
+        "kws_set_mem_limit": (C.c_int, [C.c_int64]),
+        "kws_mem_in_use": (C.c_int64, []),
         "kws_graph_info_get": (C.c_int, [P, C.POINTER(GraphInfo)]),
         "kws_profile_enable": (C.c_int, [P, C.c_int32]),
         "kws_profile_reset": (C.c_int, [P]),
@@ -191,6 +193,16 @@ def declared_symbols() -> List[str]:
     inc = os.path.join(os.path.dirname(HERE), "include")
     text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     return sorted(set(re.findall(r"\b(kws_[a-z_]+)\s*\(", text)))
+
+
+def set_mem_limit(nbytes: int) -> None:
+    """Process-wide cap on the library's device memory (negative: no cap)."""
+    _check(load_library().kws_set_mem_limit(int(nbytes)))
+
+
+def mem_in_use() -> int:
+    """Device bytes the library holds right now."""
+    return int(load_library().kws_mem_in_use())
 
 
 def last_error() -> str:

@@ -65,6 +65,38 @@ def test_empty_and_edgeless(K):
         check_same(K, 4, e, e, np.zeros(0, np.int64), vw, metric, 1, 10, f"edgeless {metric}")
 
 
+def test_fd_golden_hand_derived(K):
+    """The device's own FD weights (computed from degrees at load) give the
+    hand-derived rounds, sizes and f values of tests/golden/fd_weights.json."""
+    from test_peel_pins import load_fd_golden
+    gd = load_fd_golden()
+    n = gd["n"]
+    src = np.array([e[0] for e in gd["edges"]], np.int32)
+    dst = np.array([e[1] for e in gd["edges"]], np.int32)
+    vw = np.array(gd["vertex_w"], np.int64)
+    for case in gd["cases"]:
+        G = K.PeelGraph(n, src, dst, "FD", edge_w=None, vertex_w=vw)
+        pr, sizes, fs, sm = G.peel(case["k"], case["eps_num"], case["eps_den"])
+        G.close()
+        assert pr.tolist() == case["peel_round"], case
+        assert sizes.tolist() == case["sizes"] and fs.tolist() == case["f"], case
+        assert sm["rounds"] == case["rounds"] and sm["best"] == case["best"], case
+
+
+def test_threshold_below_two_is_rejected(K):
+    n = 6
+    src = np.arange(n, dtype=np.int32)
+    dst = ((np.arange(n) + 1) % n).astype(np.int32)
+    G = K.PeelGraph(n, src, dst, "DG")
+    for k, num, den in [(1, 0, 1), (1, 9, 10)]:
+        with pytest.raises(K.KwsError) as ei:
+            G.peel(k, num, den)
+        assert ei.value.status == K.EINVAL
+    pr, sizes, fs, sm = G.peel(1, 1, 1)
+    G.close()
+    assert sm["rounds"] == 1 and (pr == 1).all() and sizes.tolist() == [6, 0]
+
+
 @pytest.mark.parametrize("name,scale", [("peel_chunglu10k", None), ("peel_rmat20", 14), ("peel_rmat20", 16)])
 def test_synthetic_graphs(K, name, scale):
     inp = workloads.peel_input(name, scale=scale)

@@ -168,6 +168,58 @@ def test_fd_weights_follow_the_formula():
         assert oracle.load().orc_fd_weight(d) == round((1 << 24) / math.log(d + 5))
 
 
+def load_fd_golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fd_weights.json")) as f:
+        return json.load(f)
+
+
+def test_fd_golden_hand_derived():
+    """FD edge weights, peeling weights and rounds against literal values
+    derived by hand (tests/golden/fd_weights.json): the source's total
+    degree, natural log, + 5, 2^-24 units. No formula is recomputed here."""
+    gd = load_fd_golden()
+    n = gd["n"]
+    src = np.array([e[0] for e in gd["edges"]], np.int32)
+    dst = np.array([e[1] for e in gd["edges"]], np.int32)
+    vw = np.array(gd["vertex_w"], np.int64)
+    c, a = oracle.metric_weights("FD", src, dst, n, None, vw)
+    assert c.tolist() == gd["c"]
+    assert a.tolist() == gd["vertex_w"]
+    for case in gd["cases"]:
+        r = oracle.peel(n, src, dst, c, a, case["k"], case["eps_num"], case["eps_den"])
+        assert r.peel_round.tolist() == case["peel_round"], case
+        assert r.sizes.tolist() == case["sizes"] and r.f.tolist() == case["f"], case
+        assert r.rounds == case["rounds"] and r.best == case["best"], case
+    # the literal peeling weights are consistent with the literal c and a
+    # (each edge adds to both endpoints) and with f(V)
+    w = list(gd["vertex_w"])
+    for (s, d), ce in zip(gd["edges"], gd["c"]):
+        w[s] += ce
+        w[d] += ce
+    assert w == gd["w0"]
+    assert sum(gd["w0"]) == 2 * sum(gd["c"]) + sum(gd["vertex_w"])
+    assert gd["cases"][0]["f"][0] == sum(gd["c"]) + sum(gd["vertex_w"])
+
+
+def test_threshold_below_two_is_rejected():
+    """k (1 + eps) < 2 cannot guarantee progress (Algorithm 2 on a regular
+    graph with k = 1, eps = 0 peels nothing: every weight is exactly 2 g),
+    so both readings of it are refused; k (1 + eps) = 2 exactly is allowed."""
+    n = 6
+    src = np.arange(n, dtype=np.int32)
+    dst = ((np.arange(n) + 1) % n).astype(np.int32)        # directed cycle: every w = 2 = 2 g
+    c, a = oracle.metric_weights("DG", src, dst, n)
+    for k, num, den in [(1, 0, 1), (1, 9, 10)]:
+        with pytest.raises(ValueError):
+            oracle.peel(n, src, dst, c, a, k, num, den)
+        with pytest.raises(ValueError):
+            oracle.peel_opt(n, src, dst, c, a, k, num, den, mode="lpo")
+    r = oracle.peel(n, src, dst, c, a, 1, 1, 1)            # k (1 + eps) = 2: all peeled at once
+    assert r.rounds == 1 and (r.peel_round == 1).all()
+
+
 def test_uniform_generator():
     x = gen.uniform_i64(7, 1, 20000, 1, 1000)
     assert x.min() >= 1 and x.max() <= 1000 and abs(x.mean() - 500.5) < 10
