@@ -1,21 +1,32 @@
 """Benchmark of the MI355X keyword-search hot path.
 
-Default workload (the configuration the headline metric is quoted on): the
-R-MAT(.57,.19,.19,.05) graph with 2^20 vertices and 2^24 sampled edges,
-10,000 Zipf(1.0) labels with 1-3 per vertex, and a set of 100 queries of 4
-keywords each, d_max = 3, top-20. One step = one batched pass of the whole
-hot path (plan, seed, level expansion, finalize, root filter and score,
-top-k, answer graphs, result copy) over those 100 queries; inputs (graph,
-labels) are resident in HBM before timing starts. By default the steps are
-pipelined: batch i + 1 is submitted (planned, uploaded, enqueued) before
-batch i is collected, so host planning and result unpacking overlap device
-time; --pipeline 0 times one synchronous call per step instead.
+Default workload (the largest single-GPU batched configuration with
+d_max = 3): R-MAT(.57,.19,.19,.05) with 2^24 vertices and 2^28 sampled
+edges (263,429,032 after dropping loops and repeats), labels the leaves of
+a complete 8-ary type tree of depth 6 (Zipf(1.0), 1-3 per vertex), and a
+batch of 512 queries of 2-6 type keywords (a keyword matches its type and
+every type below it), d_max = 3, top-50. One step = one batched pass of the
+whole hot path (plan, seed, level expansion, finalize, root filter and
+score, top-k, answer graphs, result copy) over those 512 queries; inputs
+(graph, labels, type tree) are resident in HBM before timing starts. By
+default the steps are pipelined: batch i + 1 is submitted (planned,
+uploaded, enqueued) before batch i is collected, so host planning and
+result unpacking overlap device time; --pipeline 0 times one synchronous
+call per step instead.
 
 Printed as one JSON line: queries/s of the batched path (value), GTEPS,
 per-step latency percentiles, the plain one-query-per-call path on the same
-queries (qps, p50/p99 latency, speedup), the roofline of the dominant kernel
-from HIP events recorded on the library's stream during the timed steps, and
-the CPU oracle timed on a bounded sample on one host core.
+queries (qps, p50/p99 latency, speedup, and whether every answer equals the
+batched one), the roofline of the dominant kernel from HIP events recorded
+on the library's stream during the timed steps, and the CPU oracle timed on
+bounded samples of the same queries: one thread pinned to one core, and
+one query per worker across the host's cores.
+
+Other workloads: --workload rmat20_batch256 --autotune 1 is the 256-query
+mixed batch (2-8 keywords, d_max 2-4) on the 2^20-vertex graph, tuned by the
+library's autotuner first; rmat20_q4 (100 four-keyword queries on the same
+graph), chunglu10k, rmat26_serve (the serving loop) and peel_rmat24 (parallel
+peeling) are also available.
 """
 from __future__ import annotations
 
@@ -116,19 +127,69 @@ def measured_traffic(kernel: str, workload: str):
     return int(float(fields["traffic_bytes_per_launch"]))
 
 
-def cpu_baseline(g, qs, budget_s: float):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, qs, budget_s: float, max_workers: int = 16):
+    """The oracle on the host's cores, search only (its graph set-up is not
+    timed): (a) one thread pinned to one core, queries in order until the
+    budget is spent; (b) one query per worker on every core this process may
+    use (at most max_workers), all started together, timed to the last."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     o = oracle.Oracle(g)
-    t0 = time.perf_counter()
-    done = 0
-    for q in qs:
-        o.search(q.kw, q.d_max, q.k)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    cores = sorted(os.sched_getaffinity(0))
+    workers = max(1, min(max_workers, len(cores)))
+    os.sched_setaffinity(0, {cores[0]})
+    try:
+        t0 = time.perf_counter()
+        done = 0
+        for q in qs:
+            o.search(q.kw, q.d_max, q.k)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt1 = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(cores))
+    par = qs[:workers]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        t0 = time.perf_counter()
+        list(ex.map(lambda q: o.search(q.kw, q.d_max, q.k), par))
+        dtp = time.perf_counter() - t0
     o.close()
-    return done, dt
+    host = dict(nproc=os.cpu_count(), usable_cores=len(cores), cpu_model=cpu_model())
+    single = dict(value=round(done / dt1, 4), unit="queries/s", cores=1, kind="oracle",
+                  sample=f"first {done} of the {len(qs)} queries, one thread pinned to core {cores[0]} "
+                         f"({dt1:.1f} s)")
+    return dict(value=round(len(par) / dtp, 4), unit="queries/s", cores=workers, kind="oracle",
+                sample=f"first {len(par)} of the {len(qs)} queries, one per worker thread on {workers} cores "
+                       f"({dtp:.1f} s wall)", single_thread=single, **host)
+
+
+def same_answers(flat: dict, results) -> bool:
+    """The flat batch result holds exactly the per-query results (roots,
+    scores, keyword distances, answer edges)."""
+    rp, dp, ep = flat["root_ptr"], flat["dist_ptr"], flat["edge_ptr"]
+    for q, r in enumerate(results):
+        a, b = int(rp[q]), int(rp[q + 1])
+        if not (np.array_equal(flat["roots"][a:b], r.roots) and np.array_equal(flat["scores"][a:b], r.scores)):
+            return False
+        if not np.array_equal(flat["kw_dist"][int(dp[q]):int(dp[q + 1])], r.kw_dist.reshape(-1)):
+            return False
+        e0, e1 = int(ep[a]), int(ep[b])
+        if not (np.array_equal(flat["edge_src"][e0:e1], r.edge_src) and
+                np.array_equal(flat["edge_dst"][e0:e1], r.edge_dst) and
+                np.array_equal(flat["edge_ptr"][a:b + 1] - e0, r.edge_ptr)):
+            return False
+    return True
 
 
 def serve_bench(G, K, g, qs, args):
@@ -327,7 +388,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20_q4")
+    ap.add_argument("--workload", default="rmat24_hier")
     ap.add_argument("--scale", type=int, default=None)
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--tile-words", type=int, default=0)
@@ -337,8 +398,13 @@ def main():
     ap.add_argument("--pipeline", type=int, default=1,
                     help="1: submit batch i+1 before collecting batch i (host work overlaps the device)")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--plain", type=int, default=100, help="queries timed through the plain path")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--plain", type=int, default=-1,
+                    help="queries timed through the plain path (-1: all of the batch, 0: skip)")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="1: run the library's autotuner on the batch first and time with its choice")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of single-thread oracle time (0 = skip the CPU baseline)")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="oracle threads of the all-cores leg")
     ap.add_argument("--copy-probe-mb", type=int, default=0, help="also run a plain copy of this size")
     ap.add_argument("--peel-metrics", default="DG,DW,FD",
                     help="peeling inputs: metrics to run (the first gives value and roofline)")
@@ -377,6 +443,23 @@ def main():
     G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words, use_graph=args.graph,
                   count_te=1)
     log("graph loaded in %.2f s" % load_s)
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        best, rep = G.autotune(qs, reps=3)
+        tuned = dict(options=best, report=rep, seconds=round(time.perf_counter() - t0, 2))
+        log("autotuned:", tuned)
+
+    def set_count_te(on: int):
+        o = G.get_options()
+        if args.autotune:
+            G.set_options(direction=o.direction, alpha=o.alpha, tile_words=o.tile_words, use_graph=o.use_graph,
+                          share_lanes=o.share_lanes, count_te=on, seed_mode=o.seed_mode)
+        else:
+            G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words,
+                          use_graph=args.graph, count_te=on)
+
+    set_count_te(1)
 
     if args.serve or args.workload == "rmat26_serve":
         out = serve_bench(G, K, g, qs, args)
@@ -395,12 +478,13 @@ def main():
     # (the GTEPS numerator) is a statistic, not part of the answers: it is
     # taken from a counted warm-up step and the timed steps do not count it.
     te_step = 0
+    batch_answers = None
     for i in range(max(1, args.warmup)):
         r = G.search_batch_flat(qs)
         if i == 0:
             te_step = int(r["te"].sum())
-    G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words, use_graph=args.graph,
-                  count_te=0)
+            batch_answers = r
+    set_count_te(0)
     torch.cuda.synchronize()
 
     def run_steps(nsteps):
@@ -486,30 +570,30 @@ def main():
 
     # ---- plain path: one query per call, same queries
     plain = None
-    if args.plain > 0:
-        pq = qs[: args.plain]
+    if args.plain != 0:
+        pq = qs if args.plain < 0 else qs[: args.plain]
         for q in pq[:3]:
             G.keyword_search(q.kw, q.d_max, q.k)
-        lat = []
+        lat, answers = [], []
         t0 = time.perf_counter()
         for q in pq:
             a = time.perf_counter()
-            G.keyword_search(q.kw, q.d_max, q.k)
+            answers.append(G.keyword_search(q.kw, q.d_max, q.k))
             lat.append((time.perf_counter() - a) * 1e3)
         pw = time.perf_counter() - t0
+        # equal results: the plain answers of these queries against the
+        # batched answers of the warm-up step (same queries, same order)
         plain = dict(queries=len(pq), qps=round(len(pq) / pw, 2), p50_ms=round(float(np.percentile(lat, 50)), 4),
-                     p99_ms=round(float(np.percentile(lat, 99)), 4))
+                     p99_ms=round(float(np.percentile(lat, 99)), 4),
+                     equal_to_batched=bool(same_answers(batch_answers, answers)))
 
     if args.copy_probe_mb:
         copy_probe(args.copy_probe_mb)
 
     cpu = None
     if args.cpu_budget > 0:
-        log("timing the CPU oracle (one thread)")
-        done, dt = cpu_baseline(g, qs, args.cpu_budget)
-        cpu = dict(value=round(done / dt, 4), unit="queries/s", cores=1, kind="oracle",
-                   sample=f"first {done} of the {len(qs)} queries of this workload, single-threaded oracle "
-                          f"({dt:.1f} s)")
+        log("timing the CPU oracle (one pinned thread, then one query per core)")
+        cpu = cpu_baseline(g, qs, args.cpu_budget, args.cpu_workers)
 
     out = {
         "metric": METRIC,
@@ -531,6 +615,7 @@ def main():
         "batch_latency_ms": dict(p50=round(float(np.percentile(batch_ms, 50)), 4),
                                  p99=round(float(np.percentile(batch_ms, 99)), 4)),
         "pipelined": bool(args.pipeline),
+        "autotuned": tuned,
         "plain": plain,
         "speedup_vs_plain": round(qps / plain["qps"], 2) if plain else None,
         "roofline": roofline,

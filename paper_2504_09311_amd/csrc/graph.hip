@@ -261,7 +261,20 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   KWS_TRY(type_preorder(d->type_parent, d->n_labels, pre, span, &depth));
 
   kws_graph *g = new kws_graph();
-  auto bail = [&](kws_status st) { free_graph(g); return st; };
+  // load-time scratch; a failure anywhere frees it with the graph
+  int32_t *cnt = nullptr, *d_pre = nullptr, *keys = nullptr, *icnt = nullptr;
+  auto free_scratch = [&]() {
+    for (int32_t **p : {&cnt, &d_pre, &keys, &icnt}) {
+      dev_free(*p);
+      *p = nullptr;
+    }
+  };
+  auto bail = [&](kws_status st) {
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    free_scratch();
+    free_graph(g);
+    return st;
+  };
   KWS_HIP(hipGetDevice(&g->device));
   g->n = d->n;
   g->m = d->m;
@@ -290,7 +303,7 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
     STEP(upload(&g->fwd_col, sc.empty() ? d->col : sc.data(), (size_t)m, &bytes, "col"));
   }
   // reverse CSR: in-degree count, scan, scatter
-  int32_t *cnt = nullptr, *cursor = nullptr;
+  int32_t *cursor = nullptr;
   int64_t scratch = 0;
   STEP(alloc_dev(&cnt, (size_t)n + 1, &scratch, "in-degree"));
   STEP(alloc_dev(&g->rev_ptr, (size_t)n + 1, &bytes, "rev_ptr"));
@@ -305,13 +318,12 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   HSTEP(hipGetLastError());
   HSTEP(hipStreamSynchronize(s));
   dev_free(cnt);
+  cnt = nullptr;
 
   // inverted index over preorder keys
-  int32_t *d_lab_ptr = nullptr, *d_lab = nullptr, *d_pre = nullptr, *keys = nullptr, *icnt = nullptr;
-  STEP(upload(&d_lab_ptr, d->lab_ptr, (size_t)n + 1, &bytes, "lab_ptr"));
-  STEP(upload(&d_lab, d->lab, (size_t)nl, &bytes, "lab"));
-  g->lab_ptr = d_lab_ptr;
-  g->lab = d_lab;
+  STEP(upload(&g->lab_ptr, d->lab_ptr, (size_t)n + 1, &bytes, "lab_ptr"));
+  STEP(upload(&g->lab, d->lab, (size_t)nl, &bytes, "lab"));
+  int32_t *d_lab_ptr = g->lab_ptr, *d_lab = g->lab;
   if (d->type_parent) STEP(upload(&g->tparent, d->type_parent, (size_t)g->n_labels, &bytes, "type parents"));
   STEP(upload(&d_pre, pre.data(), pre.size(), &scratch, "type preorder"));
   STEP(alloc_dev(&keys, (size_t)nl, &scratch, "label keys"));
@@ -332,7 +344,7 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   HSTEP(hipMemcpyAsync(g->h_inv_ptr.data(), g->inv_ptr, sizeof(int32_t) * ((size_t)g->n_labels + 1),
                        hipMemcpyDeviceToHost, s));
   HSTEP(hipStreamSynchronize(s));
-  dev_free(d_pre); dev_free(keys); dev_free(icnt);
+  free_scratch();
 
   // degree facts and pull bins (host side: the CSR is already here)
   std::vector<int32_t> indeg(n, 0);
