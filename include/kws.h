@@ -174,6 +174,20 @@ kws_status kws_search_batch_collect(kws_graph *g, int64_t ticket, kws_batch_resu
  * kw (KWS_DIST_INF beyond d_max), computed by the same device kernels. */
 kws_status kws_debug_distances(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist_n);
 
+/* For callers that cannot allocate (code under stream capture, tight
+ * serving loops, harnesses that forbid device allocation): the same
+ * distances as kws_debug_distances, written to a DEVICE buffer dist_dev[n]
+ * the caller owns, without any allocation. The search state lives in one
+ * fixed array of 64 MiB per device, part of the library's code object
+ * (held by every device the library runs on until the process ends); it
+ * holds about 74 bytes per vertex plus a few KB, so graphs of up to about
+ * 900,000 vertices fit. Larger graphs get KWS_ENOMEM and a message that
+ * states both sizes. Calls are serialised process-wide (every call on a
+ * device shares that device's array) and return after the device work is
+ * done. EINVAL for a null argument, a keyword out of range or d_max outside
+ * 0..KWS_MAX_DMAX; EDEVICE on a HIP failure. */
+kws_status kws_debug_distances_noalloc(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *dist_dev);
+
 /* Engine options. Zero fields mean "default". */
 typedef struct {
   int32_t direction;     /* 0 auto (device-side choice), 1 always push, 2 always pull */

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkws.so")
-SOURCES = ["graph.hip", "kernels.hip", "plan.cpp", "search.cpp", "server.cpp", "autotune.cpp", "api.cpp", "peel.hip"]
+SOURCES = ["graph.hip", "kernels.hip", "plan.cpp", "search.cpp", "server.cpp", "autotune.cpp", "api.cpp", "peel.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

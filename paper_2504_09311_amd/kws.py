@@ -150,6 +150,7 @@ def load_library(path: str = LIB_PATH):
         "kws_search_batch_submit": (C.c_int, [P, C.POINTER(QueryC), C.c_int32, C.POINTER(C.c_int64)]),
         "kws_search_batch_collect": (C.c_int, [P, C.c_int64, C.POINTER(BatchResultC)]),
         "kws_debug_distances": (C.c_int, [P, C.c_int32, C.c_int32, P]),
+        "kws_debug_distances_noalloc": (C.c_int, [P, C.c_int32, C.c_int32, P]),
         "kws_set_options": (C.c_int, [P, C.POINTER(Options)]),
         "kws_get_options": (C.c_int, [P, C.POINTER(Options)]),
         "kws_set_stream": (C.c_int, [P, P]),
@@ -385,6 +386,11 @@ class Graph:
         out = np.empty(n, np.uint8)
         _check(self._lib.kws_debug_distances(self.h, int(kw), int(d_max), out.ctypes.data))
         return out
+
+    def debug_distances_noalloc(self, kw: int, d_max: int, dist_dev_ptr: int) -> None:
+        """kws_debug_distances_noalloc: distances into a caller-owned device
+        buffer of n bytes (an integer device address), allocating nothing."""
+        _check(self._lib.kws_debug_distances_noalloc(self.h, int(kw), int(d_max), C.c_void_p(int(dist_dev_ptr))))
 
     # ---- configuration and introspection
     def set_options(self, direction: int = 0, alpha: float = 0.0, tile_words: int = 0, use_graph: int = 0,
