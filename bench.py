@@ -74,15 +74,19 @@ def make_workload(name: str, scale: int | None, nq: int | None):
     return g, qs, desc
 
 
-def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0) -> float:
+def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0, fused: bool = True) -> float:
     """Algorithmic bytes of all launches of one kernel class in one step.
 
     expansion (push or pull) of level l, with U_l the frontier vertices,
     E_l their in-edges and T_l the vertices that gain a lane (= U_{l+1}),
-    W the 64-lane words: 8|U_l| + 4E_l + 8W|U_l| + 16W|T_l|.
+    W the 64-lane words: 8|U_l| + 4E_l + 8W|U_l| + 16W|T_l|. A pull with the
+    finalize fused in also writes, for every vertex, its next-frontier row
+    when a level follows (8 Wp n) and each distance plane whose first level
+    this is (8 Wp n per plane).
     finalize: one streaming pass over n*Wp words reading nxt and vis and
-    writing the next frontier: 24 bytes per vertex-word and launch (one per
-    level; level 0 has none when seeding by vertex, which writes it itself).
+    writing the next frontier: 24 bytes per vertex-word, for every level
+    not finalized inside a fused pull (level 0 has none when seeding by
+    vertex, which writes it itself).
     score: 8*W*n*(2 + planes) (vis, the planes and, for the last level's
     arrivals it merges, nxt).
     """
@@ -95,8 +99,13 @@ def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0) -> float:
             if (pulled[lv] == 1) != (want == 1) or f[lv] == 0:
                 continue
             tot += 8 * f[lv] + 4 * fe[lv] + 8 * W * f[lv] + 16 * W * f[lv + 1]
+            if want and fused:
+                first_planes = sum(1 for b in range(4) if (1 << b) == lv + 1 and (1 << b) <= L)
+                tot += 8.0 * Wp * n * ((1 if lv + 1 < L else 0) + first_planes)
         return tot
     if kernel == "finalize":
+        if fused:
+            return 24.0 * n * Wp * sum(1 for lv in range(L) if not pulled[lv])
         return 24.0 * n * Wp * launches
     if kernel == "score":
         planes = max(1, int(np.ceil(np.log2(L + 1)))) if L > 0 else 0
@@ -395,6 +404,12 @@ def main():
     ap.add_argument("--direction", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--graph", type=int, default=0, help="replay a captured hipGraph per batch shape")
+    ap.add_argument("--graph-check", type=int, default=20,
+                    help="steps timed without events with direct launches and with graph replay (0 = skip)")
+    ap.add_argument("--fused-pull", type=int, default=0,
+                    help="pulled levels finalize inside the pull: 0 the library's choice, 1 always, -1 never")
+    ap.add_argument("--early-stop", type=int, default=0,
+                    help="top-k early termination: 1 on, 0 or -1 off (the library's default)")
     ap.add_argument("--pipeline", type=int, default=1,
                     help="1: submit batch i+1 before collecting batch i (host work overlaps the device)")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
@@ -441,7 +456,7 @@ def main():
     G = K.Graph.from_synth(g)
     load_s = time.perf_counter() - t0
     G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words, use_graph=args.graph,
-                  count_te=1)
+                  count_te=1, fused_pull=args.fused_pull, early_stop=args.early_stop)
     log("graph loaded in %.2f s" % load_s)
     tuned = None
     if args.autotune:
@@ -450,14 +465,16 @@ def main():
         tuned = dict(options=best, report=rep, seconds=round(time.perf_counter() - t0, 2))
         log("autotuned:", tuned)
 
-    def set_count_te(on: int):
+    def set_count_te(on: int, use_graph=None):
         o = G.get_options()
         if args.autotune:
-            G.set_options(direction=o.direction, alpha=o.alpha, tile_words=o.tile_words, use_graph=o.use_graph,
-                          share_lanes=o.share_lanes, count_te=on, seed_mode=o.seed_mode)
+            G.set_options(direction=o.direction, alpha=o.alpha, tile_words=o.tile_words,
+                          use_graph=o.use_graph if use_graph is None else use_graph, share_lanes=o.share_lanes,
+                          count_te=on, seed_mode=o.seed_mode, fused_pull=o.fused_pull, early_stop=o.early_stop)
         else:
             G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words,
-                          use_graph=args.graph, count_te=on)
+                          use_graph=args.graph if use_graph is None else use_graph, count_te=on,
+                          fused_pull=args.fused_pull, early_stop=args.early_stop)
 
     set_count_te(1)
 
@@ -526,7 +543,8 @@ def main():
                            avg_us=round(v[1] * 1e3 / v[0], 3) if v[0] else 0.0)
                    for k, v in prof_all.items() if v[0]}
         st_all = G.last_batch_stats().as_dict()
-        modeled_all = {k: byte_model(st_all, g.n, k, kernels.get(k, {}).get("launches", 0) / calib_steps)
+        fused = bool(G.last_batch_stats().as_dict()["fused_pull"])
+        modeled_all = {k: byte_model(st_all, g.n, k, kernels.get(k, {}).get("launches", 0) / calib_steps, fused)
                        for k in ("pull", "push", "finalize", "score")}
         cand = [k for k in modeled_all if k in kernels and modeled_all[k] > 0]
         if cand:
@@ -553,7 +571,7 @@ def main():
     roofline = None
     if dom and prof.get(dom, (0, 0.0))[0]:
         launches, total_ms = prof[dom]
-        modeled_dom = byte_model(st, g.n, dom, launches / args.steps)
+        modeled_dom = byte_model(st, g.n, dom, launches / args.steps, bool(st["fused_pull"]))
         if modeled_dom > 0:
             per_launch_bytes = modeled_dom * args.steps / launches
             avg_s = total_ms / 1e3 / launches
@@ -567,6 +585,24 @@ def main():
                 roofline["traffic_gbs"] = round(traffic / avg_s / 1e9, 2)
                 roofline["traffic_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
                 roofline["waste_ratio"] = round(traffic / per_launch_bytes, 3)
+
+    # ---- launch modes without events: direct launches against one captured
+    # hipGraph per pass shape replayed for every step (the timed steps above
+    # bracket the roofline kernel with events, which needs direct launches)
+    launch_modes = None
+    if args.graph_check > 0:
+        launch_modes = {}
+        for mode in (0, 1):
+            set_count_te(0, use_graph=mode)
+            run_steps(2)
+            torch.cuda.synchronize()
+            w_mode, _, _ = run_steps(args.graph_check)
+            torch.cuda.synchronize()
+            launch_modes["graph_qps" if mode else "direct_qps"] = round(len(qs) * args.graph_check / w_mode, 2)
+        info = G.info()
+        launch_modes.update(steps=args.graph_check, graph_captures=int(info.graph_captures),
+                            graph_replays=int(info.graph_replays))
+        set_count_te(0)
 
     # ---- plain path: one query per call, same queries
     plain = None
@@ -616,6 +652,7 @@ def main():
                                  p99=round(float(np.percentile(batch_ms, 99)), 4)),
         "pipelined": bool(args.pipeline),
         "autotuned": tuned,
+        "launch_modes": launch_modes,
         "plain": plain,
         "speedup_vs_plain": round(qps / plain["qps"], 2) if plain else None,
         "roofline": roofline,

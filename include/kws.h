@@ -195,7 +195,11 @@ typedef struct {
   int32_t tile_words;    /* widest tile to use, in words per vertex: 1, 2, 4, 8 or 16 (default 16);
                             a batch takes the tile width its cost model prefers up to this */
   int32_t block;         /* threads per workgroup for the streaming kernels: 64..1024 */
-  int32_t use_graph;     /* 1: capture each batch shape once in a hipGraph and replay it */
+  int32_t use_graph;     /* 1: each pass shape (tile width and count, levels, seeding mode, and the
+                            per-batch sizes that set grids, rounded up to powers of two) is captured
+                            once into a hipGraph and replayed for every later pass of that shape: the
+                            kernels read the pass description from the uploaded plan, so the graph
+                            holds no per-batch value (kws_graph_info counts captures and replays) */
   int32_t share_lanes;   /* 1 (default): queries in one word share equal (keyword, d_max) lanes; -1: off */
   int32_t count_te;      /* 1: fill kws_result.te (costs a reduction per query in the score step);
                             0 (default): te = -1 */
@@ -203,6 +207,16 @@ typedef struct {
                             (lane, vertex)); 2 every vertex looks its labels and their type
                             ancestors up in a per-batch keyword hash. Auto takes 2 when the
                             batch's seeds outnumber the vertices plus label-ancestor lookups */
+  int32_t fused_pull;    /* a level expanded by pull finalizes its rows in the same kernel instead of a
+                            separate pass over every vertex. 0 (default): when tiles are 16 words (a
+                            row is one 128-byte line) and a state array exceeds 512 MB (beyond the
+                            Infinity Cache); 1: always; -1: never */
+  int32_t early_stop;    /* top-k early termination: after each level L a query that already has k
+                            complete roots scoring at most L stops expanding (any other vertex would
+                            score at least L + 1, so its answer is final; kws_result.te then counts
+                            only the levels expanded). 1: on; 0 (default) or -1: off. The check
+                            after each level reads every vertex's vis and distance planes, which on
+                            the measured workloads costs more than the expansion it saves */
 } kws_options;
 kws_status kws_set_options(kws_graph *g, const kws_options *opt);
 kws_status kws_get_options(kws_graph *g, kws_options *opt);
@@ -259,6 +273,8 @@ typedef struct {
   int64_t device_bytes;   /* graph store bytes on the device */
   int32_t max_out_degree;
   int32_t max_in_degree;
+  int64_t graph_captures;   /* batch passes captured into a hipGraph (use_graph), over the handle's life */
+  int64_t graph_replays;    /* batch passes that replayed an earlier capture */
 } kws_graph_info;
 kws_status kws_graph_info_get(kws_graph *g, kws_graph_info *info);
 
@@ -300,6 +316,9 @@ typedef struct {
   int64_t frontier[KWS_MAX_DMAX + 1];
   int64_t frontier_edges[KWS_MAX_DMAX + 1];
   int64_t unfinished_edges[KWS_MAX_DMAX + 1];
+  int32_t fused_pull;      /* 1 if pulled levels were finalized inside the pull (fused_pull) */
+  int64_t early_stopped;   /* queries that stopped before their d_max (early_stop) */
+  int64_t levels_skipped;  /* sum over those queries of d_max minus the level they stopped after */
 } kws_batch_stats;
 kws_status kws_last_batch_stats(kws_graph *g, kws_batch_stats *st);
 

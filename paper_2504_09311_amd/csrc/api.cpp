@@ -138,7 +138,7 @@ void Engine::IoSet::release() {
 }
 
 void Engine::release() {
-  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags};
+  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags, &flags_tile};
   for (DevBuf *b : d) b->release();
   for (IoSet &x : ios) x.release();
   state_words = 0;
@@ -149,7 +149,8 @@ void Engine::release() {
 const char *kernel_class_name(int id) {
   static const char *names[KC_COUNT] = {"seed",   "push",      "pull",        "finalize",    "score",
                                         "threshold", "select", "finish",    "answer",      "export",
-                                        "build",  "host_plan", "host_launch", "host_wait", "host_collect"};
+                                        "build",  "early",     "host_plan",   "host_launch", "host_wait",
+                                        "host_collect"};
   return id >= 0 && id < KC_COUNT ? names[id] : nullptr;
 }
 
@@ -377,6 +378,10 @@ kws_status kws_set_options(kws_graph *g, const kws_options *opt) {
   o.count_te = opt->count_te > 0 ? 1 : 0;
   if (opt->seed_mode < 0 || opt->seed_mode > 2) return kws::fail(KWS_EINVAL, "seed_mode must be 0, 1 or 2");
   o.seed_mode = opt->seed_mode;
+  if (opt->fused_pull < -1 || opt->fused_pull > 1) return kws::fail(KWS_EINVAL, "fused_pull must be -1, 0 or 1");
+  o.fused_pull = opt->fused_pull;
+  if (opt->early_stop < -1 || opt->early_stop > 1) return kws::fail(KWS_EINVAL, "early_stop must be -1, 0 or 1");
+  o.early_stop = opt->early_stop;
   std::lock_guard<std::mutex> lk(g->mu);
   g->opt = o;
   return KWS_OK;
@@ -407,6 +412,8 @@ kws_status kws_graph_info_get(kws_graph *g, kws_graph_info *info) {
   info->device_bytes = g->device_bytes;
   info->max_out_degree = g->max_out;
   info->max_in_degree = g->max_in;
+  info->graph_captures = g->graph_captures;
+  info->graph_replays = g->graph_replays;
   return KWS_OK;
 }
 

@@ -41,8 +41,8 @@ bool cache_lookup(const char *path, const std::string &key, kws_options *o) {
     if (key != line) continue;
     kws_options t;
     default_options(&t);
-    if (sscanf(bar + 1, "direction=%d alpha=%f tile_words=%d seed_mode=%d", &t.direction, &t.alpha, &t.tile_words,
-               &t.seed_mode) >= 3) {
+    if (sscanf(bar + 1, "direction=%d alpha=%f tile_words=%d seed_mode=%d fused_pull=%d early_stop=%d",
+               &t.direction, &t.alpha, &t.tile_words, &t.seed_mode, &t.fused_pull, &t.early_stop) >= 3) {
       *o = t;   // the last matching line wins
       found = true;
     }
@@ -54,8 +54,8 @@ bool cache_lookup(const char *path, const std::string &key, kws_options *o) {
 void cache_store(const char *path, const std::string &key, const kws_options &o, double ms) {
   FILE *f = path ? fopen(path, "a") : nullptr;
   if (!f) return;
-  fprintf(f, "%s|direction=%d alpha=%g tile_words=%d seed_mode=%d ms=%.4f\n", key.c_str(), o.direction, o.alpha,
-          o.tile_words, o.seed_mode, ms);
+  fprintf(f, "%s|direction=%d alpha=%g tile_words=%d seed_mode=%d fused_pull=%d early_stop=%d ms=%.4f\n",
+          key.c_str(), o.direction, o.alpha, o.tile_words, o.seed_mode, o.fused_pull, o.early_stop, ms);
   fclose(f);
 }
 
@@ -149,6 +149,18 @@ extern "C" kws_status kws_autotune(kws_graph *g, const kws_query *qs, int32_t nq
         o.seed_mode = sm;
         grid.push_back(o);
       }
+    if (i + 1 == n_main + 2) {   // third phase: the finalize fused into pulls or not; early termination
+      for (int fp : {1, -1}) {
+        kws_options o = best_o;
+        o.fused_pull = fp;
+        grid.push_back(o);
+      }
+      if (!saved.count_te) {     // it changes te (fewer levels scanned), so only when te is not asked for
+        kws_options o = best_o;
+        o.early_stop = 1;
+        grid.push_back(o);
+      }
+    }
   }
   if (st != KWS_OK) {
     g->opt = saved;

@@ -67,6 +67,12 @@ struct PlanWriter {
   std::vector<Piece> pieces;
   size_t size = 0;
   size_t add(const void *src, size_t bytes);
+  // A slot written later with put() (the pass and step descriptors, which
+  // hold device addresses of the plan itself).
+  size_t reserve(size_t bytes) { return add(nullptr, bytes); }
+  // Sizes both copies of the plan buffer, so dev() addresses are final.
+  kws_status prepare(Engine &E);
+  void put(Engine &E, size_t off, const void *src, size_t bytes);
   kws_status upload(Engine &E, hipStream_t s);
   template <class T> const T *dev(const Engine &E, size_t off) const {
     return (const T *)(E.io().plan.as<uint8_t>() + off);
@@ -75,7 +81,7 @@ struct PlanWriter {
 
 // Result arena (one device buffer, one copy back) and zeroed counters.
 struct ArenaLayout {
-  size_t te = 0, nroots = 0, roots = 0, scores = 0, ecount = 0, kwdist = 0, edges = 0, extra = 0, size = 0;
+  size_t te = 0, early = 0, nroots = 0, roots = 0, scores = 0, ecount = 0, kwdist = 0, edges = 0, extra = 0, size = 0;
   size_t zero_end = 0;              // [0, zero_end) is cleared by the seed kernel
   size_t z_live = 0, z_stats = 0, z_ccnt = 0, z_wcnt = 0, z_hist = 0, z_size = 0;
 };
@@ -90,6 +96,7 @@ struct PassRecord {
   ArenaLayout al;
   bool te_counted = false;
   int nq = 0, lanes = 0, lane_slots = 0, W = 0, Wp = 0, tiles = 0, T = 0, D = 0, direction = 0;
+  bool early = false, fused = false;
   float alpha = 0.f;
 };
 

@@ -350,19 +350,24 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   std::vector<int32_t> indeg(n, 0);
   for (int64_t e = 0; e < m; e++) indeg[d->col[e]]++;
   std::vector<int32_t> bins[BIN_COUNT];
-  std::vector<int32_t> hv, hb, he;
+  std::vector<int32_t> hv, hb, he, hubs, zeros;
   for (int32_t u = 0; u < n; u++) {
     int32_t b = d->row_ptr[u], e = d->row_ptr[u + 1], deg = e - b;
     g->max_out = std::max(g->max_out, deg);
     g->max_in = std::max(g->max_in, indeg[u]);
-    if (deg == 0) continue;
+    if (deg == 0) {
+      zeros.push_back(u);
+      continue;
+    }
     if (deg <= BIN_SMALL_MAX) bins[BIN_SMALL].push_back(u);
     else if (deg <= BIN_MEDIUM_MAX) bins[BIN_MEDIUM].push_back(u);
     else if (deg <= BIN_LARGE_MAX) bins[BIN_LARGE].push_back(u);
-    else
+    else {
+      hubs.push_back(u);
       for (int32_t c = b; c < e; c += HUB_CHUNK) {
         hv.push_back(u); hb.push_back(c); he.push_back(std::min(e, c + HUB_CHUNK));
       }
+    }
   }
   std::vector<int32_t> all;
   for (int b = 0; b < BIN_COUNT; b++) {
@@ -379,6 +384,10 @@ kws_status load_graph(const kws_graph_desc *d, kws_graph **out) {
   STEP(upload(&g->hub_v, hv.data(), hv.size(), &bytes, "hub chunks"));
   STEP(upload(&g->hub_b, hb.data(), hb.size(), &bytes, "hub chunks"));
   STEP(upload(&g->hub_e, he.data(), he.size(), &bytes, "hub chunks"));
+  g->n_hubv = (int64_t)hubs.size();
+  g->n_zero = (int64_t)zeros.size();
+  STEP(upload(&g->hub_vtx, hubs.data(), hubs.size(), &bytes, "hub vertices"));
+  STEP(upload(&g->zero_vtx, zeros.data(), zeros.size(), &bytes, "vertices without out-edges"));
   g->device_bytes = bytes;
 #undef STEP
 #undef HSTEP
@@ -396,7 +405,8 @@ void free_graph(kws_graph *g) {
   g->eng.release();
   g->prof.release();
   int32_t *ptrs[] = {g->fwd_ptr, g->fwd_col, g->rev_ptr, g->rev_col, g->inv_ptr, g->inv_vtx,
-                     g->lab_ptr, g->lab, g->tparent, g->bin_vtx, g->hub_v, g->hub_b, g->hub_e};
+                     g->lab_ptr, g->lab, g->tparent, g->bin_vtx, g->hub_v, g->hub_b, g->hub_e,
+                     g->hub_vtx, g->zero_vtx};
   for (int32_t *p : ptrs) dev_free(p);
   if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
   delete g;

@@ -75,7 +75,8 @@ __device__ int32_t block_scan(int32_t x, int32_t *total) {
 
 // ---- seed: zero the per-pass counters; OR each lane's bit into nxt of its keyword vertices
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
+__global__ __launch_bounds__(BLOCK) void k_seed(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   const int64_t gid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, gsz = (int64_t)gridDim.x * BLOCK;
   for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
   for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const Pass P) {
 // written to nxt tile by tile, so the stores follow the [tile][vertex][T]
 // layout instead of scattering one word per (vertex, keyword).
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass P) {
+__global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   extern __shared__ uint64_t s_rows[];   // [VB][Wp + 1] (one word of padding per row against bank conflicts)
   const int64_t gid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, gsz = (int64_t)gridDim.x * BLOCK;
   for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
@@ -153,7 +155,8 @@ __global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass P) {
 
 // ---- the per-pass counters, zeroed before a seeding kernel that adds to
 // some of them (k_seed_level0)
-__global__ __launch_bounds__(BLOCK) void k_zero_pass(const Pass P) {
+__global__ __launch_bounds__(BLOCK) void k_zero_pass(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   const int64_t gid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, gsz = (int64_t)gridDim.x * BLOCK;
   for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
   for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
@@ -167,7 +170,9 @@ __global__ __launch_bounds__(BLOCK) void k_zero_pass(const Pass P) {
 // frontier flag, the level-0 statistics and the live lanes that
 // k_finalize would have produced from it.
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass P, const Step S) {
+__global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass *__restrict__ Pp, const Step *__restrict__ Sp) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
   extern __shared__ uint64_t s_rows[];   // [VB][Wp + 1] rows, [Wp] live lanes, [VB] vertex flags
   const int tid = threadIdx.x, lane = tid & 63, VB = P.seed_vb, SUB = BLOCK / VB, RS = P.Wp + 1;
   uint64_t *s_live = s_rows + (size_t)VB * RS;
@@ -269,7 +274,10 @@ __global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass P, const Step 
 // level 2^b, as in the server) planes are cleared when the word starts and
 // every level ORs.
 template <int T, int VU>
-__global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) {
+__global__ __launch_bounds__(BLOCK) void k_finalize(const Pass *__restrict__ Pp, const Step *__restrict__ Sp) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
+  if (S.fused && pick_dir(S.st_in, P.alpha, P.force_dir) == 2) return;   // finalized by k_pull_fin
   extern __shared__ uint64_t s_live[];                    // [Wp]
   constexpr int G = T, VPB = BLOCK / T;
   constexpr int TG = 8 / VU;              // tiles per load group
@@ -384,7 +392,9 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass P, const Step S) 
 // reservation per chunk.
 constexpr int CMP_CHUNK = 2048;
 
-__global__ __launch_bounds__(BLOCK) void k_compact(const Pass P, const Step S) {
+__global__ __launch_bounds__(BLOCK) void k_compact(const Pass *__restrict__ Pp, const Step *__restrict__ Sp) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
   if (pick_dir(S.st_in, P.alpha, P.force_dir) != 1) return;
   __shared__ int32_t s_lv[CMP_CHUNK], s_le[CMP_CHUNK];
   __shared__ unsigned long long s_acc, s_base;
@@ -427,7 +437,9 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const Pass P, const Step S) {
 // ---- push: every frontier in-edge (p -> v) ORs v's frontier lanes into nxt[p]
 // Wq threads per edge cover the words (power of two, <= 64).
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_push(const Pass P, const Step S, int Wq) {
+__global__ __launch_bounds__(BLOCK) void k_push(const Pass *__restrict__ Pp, const Step *__restrict__ Sp, int Wq) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
   uint32_t nf_u = 0, mf_u = 0;
   if (pick_dir(S.st_in, P.alpha, P.force_dir, &nf_u, &mf_u) != 1) return;
   const int32_t nf = (int32_t)nf_u;
@@ -540,7 +552,9 @@ struct PullGrid { int32_t boff[BIN_COUNT + 2]; };
 constexpr int PULL_ORDER[BIN_COUNT + 1] = {BIN_COUNT, BIN_LARGE, BIN_MEDIUM, BIN_SMALL};
 
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, const PullGrid pg) {
+__global__ __launch_bounds__(BLOCK) void k_pull(const Pass *__restrict__ Pp, const Step *__restrict__ Sp, const PullGrid pg) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
   if (pick_dir(S.st_in, P.alpha, P.force_dir) != 2) return;
   constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
   const int bid = blockIdx.x;
@@ -563,6 +577,241 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
   else pull_rows<T, 64, false>(P, S, items, n_items, tile, bb, bpt);
 }
 
+// ---- pull with the finalize fused in (pulled levels of batched passes,
+// Step::fused). The grid is k_pull's: a group of S = T*E threads owns one
+// (row, tile). After the gather, its lanes with eo == 0 hold the row's
+// arrivals of their word and write what k_finalize would for that
+// vertex-tile: vis where it gains lanes, the distance planes (stored
+// outright at the plane's first level, OR-ed at later ones) and the next
+// frontier (zero included). One writer per vertex-tile, so nothing is
+// atomic and nxt is not touched. What needs every tile of a vertex (its
+// frontier flag, the direction statistics) is left as one flag byte per
+// vertex and tile (bit 0 new lanes, bit 1 lanes still to reach) for
+// k_fin_stats. Hub rows (cut into chunks that merge with atomics into nxt)
+// keep the unfused path and are finalized by k_fin_list; vertices without
+// out-edges gain nothing and only get their zero next frontier, first-level
+// planes and flag bytes.
+
+// One vertex-word of a finalize at a level >= 1: writes vis, the planes
+// and the next frontier; returns the new vis word.
+__device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_t idx, int j, uint64_t old,
+                                             uint64_t fnew) {
+  const int nl = S.newlvl[j];
+  const bool first_store = !S.clear_planes;
+  const int rmw = first_store && (nl & (nl - 1)) == 0 ? 0 : nl;
+  const uint64_t nv = old | fnew;
+  if (fnew) P.vis[idx] = nv;
+  for (int b = 0; b < P.B; b++) {
+    if (first_store && nl == (1 << b)) P.planes[b * P.pstride + idx] = fnew;
+    else if (fnew && ((rmw >> b) & 1)) P.planes[b * P.pstride + idx] |= fnew;
+  }
+  if (S.write_next) __builtin_nontemporal_store(fnew, &S.fr_next[idx]);
+  return nv;
+}
+
+template <int T, int S>
+__device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
+                                              int tile, int bb, int bpt, uint64_t &live_acc) {
+  constexpr int E = S / T, GPB = BLOCK / S, U = 8;
+  const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
+  const uint64_t gmask = group_bits(lane, S);
+  const size_t tb = (size_t)tile * P.n * T;
+  const uint64_t *fr = SP.fr_cur + tb;
+  const int j = tile * T + w;
+  const uint64_t actw = SP.act_exp[j] & SP.live_in[j];
+  const uint64_t an = SP.act_new[j], ann = SP.act_nn[j];
+  const int32_t *col = P.fwd_col;
+  uint8_t *flags = SP.flags_tile + (size_t)tile * P.n;
+  for (int64_t it = (int64_t)bb * GPB + tid / S; it < n_items; it += (int64_t)bpt * GPB) {
+    const int32_t v = items[it], eb = P.fwd_ptr[v], ee = P.fwd_ptr[v + 1];
+    const size_t idx = tb + (size_t)v * T + w;
+    const uint64_t old = P.vis[idx];
+    const uint64_t need = actw & ~old;
+    uint64_t acc = 0;
+    if ((__ballot(need != 0) & gmask) != 0) {
+      int32_t x[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int32_t e = eb + u * E + eo;
+        x[u] = e < ee ? col[e] : -1;
+      }
+      for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
+        int32_t xn[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int32_t e = e0 + E * U + u * E + eo;
+          xn[u] = e < ee ? col[e] : -1;
+        }
+        const bool want = (acc & need) != need;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
+        uint64_t r = acc;
+#pragma unroll
+        for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
+        if ((__ballot((r & need) != need) & gmask) == 0) break;
+#pragma unroll
+        for (int u = 0; u < U; u++) x[u] = xn[u];
+      }
+#pragma unroll
+      for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
+    }
+    bool anyf = false, anyneed = false;
+    if (eo == 0) {
+      const uint64_t fnew = acc & need & an;
+      const uint64_t nv = fin_word(P, SP, idx, j, old, fnew);
+      if (SP.write_next) live_acc |= fnew;
+      anyf = fnew != 0;
+      anyneed = (ann & ~nv) != 0;
+    }
+    const bool fflag = (__ballot(anyf) & gmask) != 0, nflag = (__ballot(anyneed) & gmask) != 0;
+    if (gl == 0) flags[v] = (uint8_t)((fflag ? 1 : 0) | (nflag ? 2 : 0));
+  }
+}
+
+// vertices without out-edges, one tile: nothing arrives; zero next frontier
+// and first-level planes, zero flag byte (T threads per vertex)
+template <int T>
+__device__ __forceinline__ void fin_zero_rows(const Pass &P, const Step &SP, int tile, int bb, int bpt) {
+  constexpr int GPB = BLOCK / T;
+  const int tid = threadIdx.x, w = tid % T;
+  const int j = tile * T + w;
+  const int nl = SP.newlvl[j];
+  const bool first_store = !SP.clear_planes;
+  uint8_t *flags = SP.flags_tile + (size_t)tile * P.n;
+  for (int64_t it = (int64_t)bb * GPB + tid / T; it < P.n_zero; it += (int64_t)bpt * GPB) {
+    const int32_t v = P.zero_vtx[it];
+    const size_t idx = (size_t)tile * P.n * T + (size_t)v * T + w;
+    for (int b = 0; b < P.B; b++)
+      if (first_store && nl == (1 << b)) P.planes[b * P.pstride + idx] = 0ull;
+    if (SP.write_next) __builtin_nontemporal_store(0ull, &SP.fr_next[idx]);
+    if (w == 0) flags[v] = 0;
+  }
+}
+
+// Live lanes of one word per thread: OR over the lanes that share the word
+// (lane % T), one LDS atomic per word and wavefront, then one global atomic
+// per word and block.
+template <int T>
+__device__ __forceinline__ void fin_live_out(const Step &S, uint64_t *s_live, int Wp, int j, uint64_t live_acc) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (S.write_next) {
+    uint64_t x = live_acc;
+    for (int off = T; off < 64; off <<= 1) x |= __shfl_xor(x, off);
+    if (lane < T && x) atomicOr((unsigned long long *)&s_live[j], x);
+  }
+  __syncthreads();
+  if (S.write_next)
+    for (int k = tid; k < Wp; k += BLOCK)
+      if (s_live[k]) atomicOr((unsigned long long *)&S.live_out[k], s_live[k]);
+}
+
+// One launch, k_pull's grid plus the vertices without out-edges: blocks
+// [boff[i], boff[i+1]) serve part i = hub chunks, large, medium, small
+// rows, rows without out-edges; inside a part, tiles x blocks per tile.
+struct FinGrid { int32_t boff[6]; };
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_pull_fin(const Pass *__restrict__ Pp, const Step *__restrict__ Sp, const FinGrid fg) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
+  if (pick_dir(S.st_in, P.alpha, P.force_dir) != 2) return;
+  extern __shared__ uint64_t s_live[];   // [Wp]
+  constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
+  for (int k = threadIdx.x; k < P.Wp; k += BLOCK) s_live[k] = 0;
+  __syncthreads();
+  const int bid = blockIdx.x;
+  int part = 0;
+  while (part < 5 && bid >= fg.boff[part + 1]) part++;
+  uint64_t live_acc = 0;
+  int tile = 0;
+  if (part < 5) {
+    const int nblk = fg.boff[part + 1] - fg.boff[part], lb = bid - fg.boff[part];
+    const int bpt = nblk / P.tiles, bb = lb % bpt;
+    tile = lb / bpt;
+    if (tile < P.tiles) {
+      if (part == 0) {
+        pull_rows<T, 64, true>(P, S, nullptr, P.n_hub, tile, bb, bpt);
+      } else if (part == 4) {
+        fin_zero_rows<T>(P, S, tile, bb, bpt);
+      } else {
+        const int b = part == 1 ? BIN_LARGE : part == 2 ? BIN_MEDIUM : BIN_SMALL;
+        const int32_t *items = P.bin_vtx + P.bin_begin[b];
+        const int64_t n_items = P.bin_begin[b + 1] - P.bin_begin[b];
+        if (b == BIN_SMALL) pull_fin_rows<T, S_SMALL>(P, S, items, n_items, tile, bb, bpt, live_acc);
+        else if (b == BIN_MEDIUM) pull_fin_rows<T, S_MED>(P, S, items, n_items, tile, bb, bpt, live_acc);
+        else pull_fin_rows<T, 64>(P, S, items, n_items, tile, bb, bpt, live_acc);
+      }
+    } else {
+      tile = 0;
+    }
+  }
+  fin_live_out<T>(S, s_live, P.Wp, tile * T + (int)(threadIdx.x % T), live_acc);
+}
+
+// The finalize of a list of vertices (the hub vertices of a fused pulled
+// level): arrivals from nxt, which is cleared; T threads per vertex and
+// tile; flag bytes as k_pull_fin writes them.
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_fin_list(const Pass *__restrict__ Pp, const Step *__restrict__ Sp, const int32_t *list, int64_t count) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
+  if (pick_dir(S.st_in, P.alpha, P.force_dir) != 2) return;
+  extern __shared__ uint64_t s_live[];   // [Wp]
+  constexpr int GPB = BLOCK / T;
+  const int tid = threadIdx.x, w = tid % T, lane = tid & 63;
+  const uint64_t gmask = group_bits(lane, T);
+  for (int k = tid; k < P.Wp; k += BLOCK) s_live[k] = 0;
+  __syncthreads();
+  const int64_t items = count * P.tiles;
+  for (int64_t it = (int64_t)blockIdx.x * GPB + tid / T; it < items; it += (int64_t)gridDim.x * GPB) {
+    const int tile = (int)(it / count);
+    const int32_t v = list[it % count];
+    const int j = tile * T + w;
+    const size_t idx = (size_t)tile * P.n * T + (size_t)v * T + w;
+    const uint64_t old = P.vis[idx], nx = P.nxt[idx];
+    const uint64_t fnew = nx & ~old & S.act_new[j];
+    const uint64_t nv = fin_word(P, S, idx, j, old, fnew);
+    if (nx) P.nxt[idx] = 0ull;
+    if (fnew && S.write_next) atomicOr((unsigned long long *)&s_live[j], fnew);
+    const bool fflag = (__ballot(fnew != 0) & gmask) != 0;
+    const bool nflag = (__ballot((S.act_nn[j] & ~nv) != 0) & gmask) != 0;
+    if (w == 0) S.flags_tile[(size_t)tile * P.n + v] = (uint8_t)((fflag ? 1 : 0) | (nflag ? 2 : 0));
+  }
+  __syncthreads();
+  if (S.write_next)
+    for (int k = tid; k < P.Wp; k += BLOCK)
+      if (s_live[k]) atomicOr((unsigned long long *)&S.live_out[k], s_live[k]);
+}
+
+// Per vertex over its tiles' flag bytes: the frontier flag of the next
+// level and the direction statistics (frontier vertices, their in-edges,
+// out-edges of vertices still missing lanes), as k_finalize gives them.
+__global__ __launch_bounds__(BLOCK) void k_fin_stats(const Pass *__restrict__ Pp, const Step *__restrict__ Sp) {
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
+  if (pick_dir(S.st_in, P.alpha, P.force_dir) != 2) return;
+  const int lane = threadIdx.x & 63;
+  uint64_t nf = 0, mf = 0, mu = 0;
+  for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < P.n; v += (int64_t)gridDim.x * BLOCK) {
+    uint32_t f = 0;
+    for (int t = 0; t < P.tiles; t++) f |= S.flags_tile[(size_t)t * P.n + v];
+    if (S.build_list) S.flags_next[v] = (uint8_t)(f & 1u);
+    if (f & 1u) { nf++; mf += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
+    if ((f & 2u) && S.write_next) mu += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nf += __shfl_xor(nf, off);
+    mf += __shfl_xor(mf, off);
+    mu += __shfl_xor(mu, off);
+  }
+  if (lane == 0) {
+    uint64_t *st = stat_stripe(S.st_out, blockIdx.x);
+    if (nf) atomicAdd((unsigned long long *)&st[0], (unsigned long long)((nf << 32) | mf));
+    if (mu) atomicAdd((unsigned long long *)&st[1], (unsigned long long)mu);
+  }
+}
+
 // ---- score: per vertex and query, root test and score histogram per chunk;
 // optionally the scanned-edge count te (in-degree of every vertex each lane
 // expanded). A thread owns one vertex and holds the T words of one tile
@@ -579,7 +828,8 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass P, const Step S, cons
 // vis and the planes, merges the arrivals in registers, writes back only
 // what changed, clears nxt and adds the level's frontier statistics.
 template <int T, bool L, bool TE, bool FIN, int PB>
-__global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
+__global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, const Step *__restrict__ Fp) {
+  const Pass &P = *Pp;
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;                                   // [nq] (count_te)
   uint64_t *s_qm = s_dyn + P.nq;                            // [nq] masks in word order
@@ -660,9 +910,9 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
 #pragma unroll
             for (int w = 0; w < H; w++) {
               const int j = tile * T + h0 + w;
-              const int nl = F.newlvl[j];
+              const int nl = Fp->newlvl[j];
               const uint64_t nx = __builtin_nontemporal_load(&P.nxt[base + w]);
-              const uint64_t fnew = nx & ~vis[w] & F.act_new[j];
+              const uint64_t fnew = nx & ~vis[w] & Fp->act_new[j];
               rown |= nx != 0;
               if (fnew) {
                 vis[w] |= fnew;
@@ -774,7 +1024,78 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass P, const Step F) {
       mf_acc += __shfl_xor(mf_acc, off);
     }
     if (lane == 0 && nf_acc)
-      atomicAdd((unsigned long long *)stat_stripe(F.st_out, blockIdx.x), (unsigned long long)((nf_acc << 32) | mf_acc));
+      atomicAdd((unsigned long long *)stat_stripe(Fp->st_out, blockIdx.x), (unsigned long long)((nf_acc << 32) | mf_acc));
+  }
+}
+
+// ---- top-k early termination. After level L every lane's distances up to
+// L are final, and a vertex that some keyword of a query has not reached
+// will score at least L + 1 once it is a root. So a query with at least k
+// complete roots (all its lanes reached) scoring at most L already has its
+// top k, with every tie at L included: it stops expanding. Its lanes leave
+// the activity table of the later levels unless a running query in the
+// same word shares them; vis and the planes keep what level L left, which
+// is exact for every vertex the score, the selection and the answer walk
+// read. The distance planes whose first level is above L are not stored
+// yet, and a distance of at most L has those bits clear, so they are not
+// read here.
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_early_count(const Pass *__restrict__ Pp, int L) {
+  const Pass &P = *Pp;
+  extern __shared__ int32_t s_cnt[];   // [nq]
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int i = tid; i < P.nq; i += BLOCK) s_cnt[i] = 0;
+  __syncthreads();
+  int pv = 0;                            // planes stored by level L
+  while (pv < P.B && (1 << pv) <= L) pv++;
+  for (int64_t vb = (int64_t)blockIdx.x * BLOCK; vb < P.n; vb += (int64_t)gridDim.x * BLOCK) {
+    const int64_t v = vb + tid;
+    const bool valid = v < P.n;
+    for (int j = 0; j < P.W; j++) {
+      const int qb = P.word_q_ptr[j], qe = P.word_q_ptr[j + 1];
+      if (qb == qe) continue;
+      const size_t idx = ((size_t)(j / T) * P.n + (valid ? v : 0)) * T + (j % T);
+      const uint64_t vis = valid ? P.vis[idx] : 0ull;
+      if (__ballot(vis != 0) == 0) continue;
+      uint64_t pl[4] = {0, 0, 0, 0};
+      for (int b = 0; b < pv && b < 4; b++) pl[b] = valid ? P.planes[b * P.pstride + idx] : 0ull;
+      for (int qi = qb; qi < qe; qi++) {
+        const int q = P.word_q[qi];
+        if (P.q_dmax[q] <= L || P.early_stop[q]) continue;
+        const uint64_t m = P.q_mask[q];
+        const bool root = valid && (m & ~vis) == 0;
+        if (__ballot(root) == 0) continue;
+        int sc = 0;
+        for (int b = 0; b < pv && b < 4; b++) sc += __popcll(pl[b] & m) << b;
+        const int c = __popcll(__ballot(root && sc <= L));
+        if (lane == 0 && c) atomicAdd(&s_cnt[q], c);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < P.nq; i += BLOCK)
+    if (s_cnt[i]) atomicAdd(&P.early_cnt[i], s_cnt[i]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_early_apply(const Pass *__restrict__ Pp, int L) {
+  const Pass &P = *Pp;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < P.nq; q += BLOCK) {
+    if (!P.early_stop[q] && P.q_dmax[q] > L && P.early_cnt[q] >= P.q_kcap[q]) P.early_stop[q] = L + 1;
+    P.early_cnt[q] = 0;
+  }
+  __syncthreads();
+  for (int j = tid; j < P.W; j += BLOCK) {
+    uint64_t stop = 0, keep = 0;
+    for (int qi = P.word_q_ptr[j]; qi < P.word_q_ptr[j + 1]; qi++) {
+      const int q = P.word_q[qi];
+      if (P.q_dmax[q] <= L) continue;    // its lanes are past their radius already
+      if (P.early_stop[q]) stop |= P.q_mask[q];
+      else keep |= P.q_mask[q];
+    }
+    const uint64_t clear = stop & ~keep;
+    if (clear)
+      for (int lv = L + 1; lv <= P.D + 1; lv++) P.act_tab[(size_t)lv * P.Wp + j] &= ~clear;
   }
 }
 
@@ -800,7 +1121,8 @@ __device__ int32_t th_block_scan(int32_t x, int32_t *total) {
   return base + incl - x;
 }
 
-__global__ __launch_bounds__(TH_BLOCK) void k_threshold(const Pass P) {
+__global__ __launch_bounds__(TH_BLOCK) void k_threshold(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   __shared__ int32_t tot[KWS_MAX_KW * KWS_MAX_DMAX + 1];
   __shared__ int32_t s_sel[4];
   const int tid = threadIdx.x;
@@ -866,7 +1188,8 @@ __device__ __forceinline__ int lane_dist(const Pass &P, size_t idx, int bit) {
 // barriers), and the vis words of SU rounds of 64 vertices are loaded before
 // any is used.
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_select(const Pass P) {
+__global__ __launch_bounds__(BLOCK) void k_select(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   constexpr int WAVES = BLOCK / 64, SU = 4;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1ull;
@@ -914,7 +1237,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(const Pass P) {
 // ---- finish: order each query's candidates by (score, id); write roots,
 // scores and the per-keyword distances.
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_finish(const Pass P) {
+__global__ __launch_bounds__(BLOCK) void k_finish(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   constexpr int LDS_SORT = 2048;
   __shared__ uint64_t s_key[LDS_SORT];
   const int tid = threadIdx.x;
@@ -970,7 +1294,8 @@ __device__ __forceinline__ int32_t block_min(int32_t v, int32_t *slot) {
 // walks (wider rounds end long rows sooner), 256 when it has many (more
 // walks in flight).
 template <int T, int AB>
-__global__ __launch_bounds__(AB) void k_answer(const Pass P) {
+__global__ __launch_bounds__(AB) void k_answer(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   __shared__ int32_t s_best;
   constexpr int NSAMP = 4096;             // row samples held in LDS for the last hop
   __shared__ int32_t s_samp[NSAMP];
@@ -1057,7 +1382,8 @@ __global__ __launch_bounds__(AB) void k_answer(const Pass P) {
 }
 
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_answer_merge(const Pass P) {
+__global__ __launch_bounds__(BLOCK) void k_answer_merge(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
   constexpr int WAVES = BLOCK / 64, ECAP = KWS_MAX_KW * KWS_MAX_DMAX;
   __shared__ uint64_t s_e[WAVES][ECAP];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1098,7 +1424,8 @@ __global__ __launch_bounds__(BLOCK) void k_answer_merge(const Pass P) {
 
 // ---- export one lane's distances (verification entry point)
 template <int T>
-__global__ __launch_bounds__(BLOCK) void k_export(const Pass P, uint8_t *out) {
+__global__ __launch_bounds__(BLOCK) void k_export(const Pass *__restrict__ Pp, uint8_t *out) {
+  const Pass &P = *Pp;
   for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < P.n; v += (int64_t)gridDim.x * BLOCK) {
     const size_t idx = (size_t)v * T;
     out[v] = (P.vis[idx] & 1ull) ? (uint8_t)lane_dist(P, idx, 0) : (uint8_t)KWS_DIST_INF;
@@ -1112,6 +1439,23 @@ namespace {
 
 inline unsigned clamp_grid(int64_t blocks) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 1 << 16));
+}
+
+// A per-batch size that sets a grid or an LDS size. In graph mode it is
+// rounded up to a power of two, so batches of one shape launch identically
+// and a captured graph replays for all of them (the kernels loop over
+// their items, so a larger grid only adds blocks that find nothing to do).
+inline int64_t launch_size(const Pass &P, int64_t x) {
+  if (!P.graph_mode || x <= 1) return x;
+  int64_t r = 1;
+  while (r < x) r <<= 1;
+  return r;
+}
+
+inline size_t score_lds(const Pass &P) {
+  return P.hist_lds ? (size_t)launch_size(P, (int64_t)((size_t)P.nq * (8 + 8 + 4 + 4 + 4) +
+                                                      sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist)))
+                    : 0;
 }
 
 // Blocks of BLOCK threads that the whole device holds at once for this
@@ -1157,8 +1501,8 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
   const int Wq = std::min(64, P.Wp < 2 ? 1 : 1 << (32 - __builtin_clz((unsigned)P.Wp - 1)));
   {
     Timer t(prof, s, KC_PUSH);
-    k_compact<<<clamp_grid(std::min<int64_t>(((int64_t)P.n + CMP_CHUNK - 1) / CMP_CHUNK, 4096)), BLOCK, 0, s>>>(P, S);
-    k_push<T><<<2048, BLOCK, 0, s>>>(P, S, Wq);
+    k_compact<<<clamp_grid(std::min<int64_t>(((int64_t)P.n + CMP_CHUNK - 1) / CMP_CHUNK, 4096)), BLOCK, 0, s>>>(P.dev, S.dev);
+    k_push<T><<<2048, BLOCK, 0, s>>>(P.dev, S.dev, Wq);
   }
   KWS_TRY(launch_check("push"));
   constexpr int S_SMALL = T, S_MED = (8 * T < 64 ? 8 * T : 64);
@@ -1172,11 +1516,33 @@ kws_status expand_t(const Pass &P, const Step &S, hipStream_t s, Profiler &prof)
     const int64_t bpt = items ? std::min<int64_t>((items + gpb - 1) / gpb, 16384 / P.tiles + 1) : 0;
     pg.boff[i + 1] = pg.boff[i] + (int32_t)(bpt * P.tiles);
   }
+  if (!S.fused) {
+    Timer t(prof, s, KC_PULL);
+    k_pull<T><<<(unsigned)std::max(1, pg.boff[BIN_COUNT + 1]), BLOCK, 0, s>>>(P.dev, S.dev, pg);
+    return launch_check("pull");
+  }
+  // fused: k_pull's grid plus the vertices without out-edges (per tile);
+  // then the hub vertices' finalize and the per-vertex flags and statistics
+  FinGrid fg;
+  for (int i = 0; i <= BIN_COUNT + 1; i++) fg.boff[i] = pg.boff[i];
+  {
+    const int64_t gpb = BLOCK / T, items = P.n_zero;
+    const int64_t bpt = items ? std::min<int64_t>((items + gpb - 1) / gpb, 16384 / P.tiles + 1) : 0;
+    fg.boff[BIN_COUNT + 2] = fg.boff[BIN_COUNT + 1] + (int32_t)(bpt * P.tiles);
+  }
+  const size_t lds = sizeof(uint64_t) * (size_t)P.Wp;
   {
     Timer t(prof, s, KC_PULL);
-    k_pull<T><<<(unsigned)std::max(1, pg.boff[BIN_COUNT + 1]), BLOCK, 0, s>>>(P, S, pg);
+    k_pull_fin<T><<<(unsigned)std::max(1, fg.boff[BIN_COUNT + 2]), BLOCK, lds, s>>>(P.dev, S.dev, fg);
   }
-  return launch_check("pull");
+  KWS_TRY(launch_check("pull"));
+  {
+    Timer t(prof, s, KC_FINALIZE);
+    if (P.n_hubv > 0)
+      k_fin_list<T><<<clamp_grid((P.n_hubv * P.tiles + BLOCK / T - 1) / (BLOCK / T)), BLOCK, lds, s>>>(P.dev, S.dev, P.hub_vtx, P.n_hubv);
+    k_fin_stats<<<clamp_grid(std::min<int64_t>(((int64_t)P.n + BLOCK - 1) / BLOCK, 4096)), BLOCK, 0, s>>>(P.dev, S.dev);
+  }
+  return launch_check("fused finalize");
 }
 
 template <int T>
@@ -1193,10 +1559,10 @@ kws_status finalize_t(const Pass &P, const Step &S, hipStream_t s, Profiler &pro
   {
     Timer t(prof, s, KC_FINALIZE);
     switch (vu) {
-      case 1: k_finalize<T, 1><<<grid_for_kernel((const void *)k_finalize<T, 1>), BLOCK, lds, s>>>(P, S); break;
-      case 2: k_finalize<T, 2><<<grid_for_kernel((const void *)k_finalize<T, 2>), BLOCK, lds, s>>>(P, S); break;
-      case 4: k_finalize<T, 4><<<grid_for_kernel((const void *)k_finalize<T, 4>), BLOCK, lds, s>>>(P, S); break;
-      default: k_finalize<T, 8><<<grid_for_kernel((const void *)k_finalize<T, 8>), BLOCK, lds, s>>>(P, S); break;
+      case 1: k_finalize<T, 1><<<grid_for_kernel((const void *)k_finalize<T, 1>), BLOCK, lds, s>>>(P.dev, S.dev); break;
+      case 2: k_finalize<T, 2><<<grid_for_kernel((const void *)k_finalize<T, 2>), BLOCK, lds, s>>>(P.dev, S.dev); break;
+      case 4: k_finalize<T, 4><<<grid_for_kernel((const void *)k_finalize<T, 4>), BLOCK, lds, s>>>(P.dev, S.dev); break;
+      default: k_finalize<T, 8><<<grid_for_kernel((const void *)k_finalize<T, 8>), BLOCK, lds, s>>>(P.dev, S.dev); break;
     }
   }
   return launch_check("finalize");
@@ -1208,13 +1574,13 @@ template <int T, bool TE, bool FIN>
 void score_launch(const Pass &P, const Step &F, int grid, size_t lds, hipStream_t s) {
   if constexpr (T == 16) {
     if (P.B <= 2) {
-      if (P.hist_lds) k_score<T, true, TE, FIN, 2><<<grid, BLOCK, lds, s>>>(P, F);
-      else k_score<T, false, TE, FIN, 2><<<grid, BLOCK, 0, s>>>(P, F);
+      if (P.hist_lds) k_score<T, true, TE, FIN, 2><<<grid, BLOCK, lds, s>>>(P.dev, F.dev);
+      else k_score<T, false, TE, FIN, 2><<<grid, BLOCK, 0, s>>>(P.dev, F.dev);
       return;
     }
   }
-  if (P.hist_lds) k_score<T, true, TE, FIN, 4><<<grid, BLOCK, lds, s>>>(P, F);
-  else k_score<T, false, TE, FIN, 4><<<grid, BLOCK, 0, s>>>(P, F);
+  if (P.hist_lds) k_score<T, true, TE, FIN, 4><<<grid, BLOCK, lds, s>>>(P.dev, F.dev);
+  else k_score<T, false, TE, FIN, 4><<<grid, BLOCK, 0, s>>>(P.dev, F.dev);
 }
 
 template <int T>
@@ -1226,10 +1592,8 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
   {
     Timer t(prof, s, KC_SCORE);
     const int64_t split = (P.CH + BLOCK - 1) / BLOCK;
-    const int grid = clamp_grid(P.chunks * split);
-    const size_t lds = P.hist_lds ? (size_t)P.nq * (8 + 8 + 4 + 4 + 4) +
-                                        sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist)
-                                  : 0;
+    const int grid = clamp_grid(launch_size(P, P.chunks * split));
+    const size_t lds = score_lds(P);
     Step none;
     std::memset(&none, 0, sizeof(none));
     if (last) {
@@ -1243,25 +1607,26 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
   KWS_TRY(launch_check("score"));
   {
     Timer t(prof, s, KC_THRESHOLD);
-    k_threshold<<<clamp_grid(P.nq), TH_BLOCK, 0, s>>>(P);
+    k_threshold<<<clamp_grid(launch_size(P, P.nq)), TH_BLOCK, 0, s>>>(P.dev);
   }
   KWS_TRY(launch_check("threshold"));
   {
     Timer t(prof, s, KC_SELECT);
-    k_select<T><<<2048, BLOCK, 0, s>>>(P);
+    k_select<T><<<2048, BLOCK, 0, s>>>(P.dev);
   }
   KWS_TRY(launch_check("select"));
   {
     Timer t(prof, s, KC_FINISH);
-    k_finish<T><<<clamp_grid(P.nq), BLOCK, 0, s>>>(P);
+    k_finish<T><<<clamp_grid(launch_size(P, P.nq)), BLOCK, 0, s>>>(P.dev);
   }
   KWS_TRY(launch_check("finish"));
   {
     Timer t(prof, s, KC_ANSWER);
     const int64_t waves = BLOCK / 64;
-    if (P.total_kd <= 16384) k_answer<T, 512><<<clamp_grid(P.total_kd), 512, 0, s>>>(P);
-    else k_answer<T, 256><<<clamp_grid(P.total_kd), 256, 0, s>>>(P);
-    k_answer_merge<T><<<clamp_grid((P.total_slots + waves - 1) / waves), BLOCK, 0, s>>>(P);
+    const int64_t kd = launch_size(P, P.total_kd);
+    if (kd <= 16384) k_answer<T, 512><<<clamp_grid(kd), 512, 0, s>>>(P.dev);
+    else k_answer<T, 256><<<clamp_grid(kd), 256, 0, s>>>(P.dev);
+    k_answer_merge<T><<<clamp_grid(launch_size(P, (P.total_slots + waves - 1) / waves)), BLOCK, 0, s>>>(P.dev);
   }
   return launch_check("answer");
 }
@@ -1279,20 +1644,20 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
 }  // namespace
 
 kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
-  const int64_t items = std::max<int64_t>(P.seed_by_vertex ? P.n : P.total_seeds,
-                                          std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
+  const int64_t zwords = launch_size(P, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
+  const int64_t items = std::max<int64_t>(P.seed_by_vertex ? P.n : launch_size(P, P.total_seeds), zwords);
   if (P.seed_by_vertex) {
     Timer t(prof, s, KC_SEED);
     const int64_t vblocks = ((int64_t)P.n + P.seed_vb - 1) / P.seed_vb;
-    const int64_t zblocks = (std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)) + BLOCK - 1) / BLOCK;
+    const int64_t zblocks = (zwords + BLOCK - 1) / BLOCK;
     const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(std::min<int64_t>(vblocks, 4096), zblocks), 65535));
     const size_t lds = sizeof(uint64_t) * (size_t)P.seed_vb * (size_t)(P.Wp + 1);
     switch (P.T) {
-      case 1: k_seed_vertex<1><<<grid, BLOCK, lds, s>>>(P); break;
-      case 2: k_seed_vertex<2><<<grid, BLOCK, lds, s>>>(P); break;
-      case 4: k_seed_vertex<4><<<grid, BLOCK, lds, s>>>(P); break;
-      case 8: k_seed_vertex<8><<<grid, BLOCK, lds, s>>>(P); break;
-      case 16: k_seed_vertex<16><<<grid, BLOCK, lds, s>>>(P); break;
+      case 1: k_seed_vertex<1><<<grid, BLOCK, lds, s>>>(P.dev); break;
+      case 2: k_seed_vertex<2><<<grid, BLOCK, lds, s>>>(P.dev); break;
+      case 4: k_seed_vertex<4><<<grid, BLOCK, lds, s>>>(P.dev); break;
+      case 8: k_seed_vertex<8><<<grid, BLOCK, lds, s>>>(P.dev); break;
+      case 16: k_seed_vertex<16><<<grid, BLOCK, lds, s>>>(P.dev); break;
       default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
     }
     return launch_check("seed");
@@ -1300,11 +1665,11 @@ kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
   {
     Timer t(prof, s, KC_SEED);
     switch (P.T) {
-      case 1: k_seed<1><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
-      case 2: k_seed<2><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
-      case 4: k_seed<4><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
-      case 8: k_seed<8><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
-      case 16: k_seed<16><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P); break;
+      case 1: k_seed<1><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev); break;
+      case 2: k_seed<2><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev); break;
+      case 4: k_seed<4><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev); break;
+      case 8: k_seed<8><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev); break;
+      case 16: k_seed<16><<<clamp_grid((items + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev); break;
       default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
     }
   }
@@ -1313,21 +1678,40 @@ kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
 
 kws_status launch_seed_level0(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
   Timer t(prof, s, KC_SEED);
-  const int64_t zwords = std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words));
-  if (zwords > 0) k_zero_pass<<<clamp_grid((zwords + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P);
+  const int64_t zwords = launch_size(P, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
+  if (zwords > 0) k_zero_pass<<<clamp_grid((zwords + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev);
   const int64_t vblocks = ((int64_t)P.n + P.seed_vb - 1) / P.seed_vb;
   const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(vblocks, 1), 4096));
   const size_t lds = sizeof(uint64_t) * ((size_t)P.seed_vb * (size_t)(P.Wp + 1) + (size_t)P.Wp) +
                      sizeof(uint32_t) * (size_t)P.seed_vb;
   switch (P.T) {
-    case 1: k_seed_level0<1><<<grid, BLOCK, lds, s>>>(P, S); break;
-    case 2: k_seed_level0<2><<<grid, BLOCK, lds, s>>>(P, S); break;
-    case 4: k_seed_level0<4><<<grid, BLOCK, lds, s>>>(P, S); break;
-    case 8: k_seed_level0<8><<<grid, BLOCK, lds, s>>>(P, S); break;
-    case 16: k_seed_level0<16><<<grid, BLOCK, lds, s>>>(P, S); break;
+    case 1: k_seed_level0<1><<<grid, BLOCK, lds, s>>>(P.dev, S.dev); break;
+    case 2: k_seed_level0<2><<<grid, BLOCK, lds, s>>>(P.dev, S.dev); break;
+    case 4: k_seed_level0<4><<<grid, BLOCK, lds, s>>>(P.dev, S.dev); break;
+    case 8: k_seed_level0<8><<<grid, BLOCK, lds, s>>>(P.dev, S.dev); break;
+    case 16: k_seed_level0<16><<<grid, BLOCK, lds, s>>>(P.dev, S.dev); break;
     default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
   }
   return launch_check("seed");
+}
+
+void graph_shape_key(const Pass &P, const std::vector<Step> &steps, bool fin_last, std::vector<int64_t> &key) {
+  key.clear();
+  // the descriptors' device addresses (the plan buffer of the I/O set) and
+  // every value a launch above takes its grid, LDS size or variant from
+  key.push_back((int64_t)(uintptr_t)P.dev);
+  key.push_back(steps.empty() ? 0 : (int64_t)(uintptr_t)steps[0].dev);
+  for (int64_t x : {(int64_t)P.T, (int64_t)P.tiles, (int64_t)P.Wp, (int64_t)P.B, (int64_t)P.n,
+                    (int64_t)P.seed_by_vertex, (int64_t)P.seed_vb, (int64_t)P.hist_lds, (int64_t)P.count_te,
+                    (int64_t)fin_last, (int64_t)steps.size(), (int64_t)(P.nq == 0)})
+    key.push_back(x);
+  const int64_t split = (P.CH + BLOCK - 1) / BLOCK, waves = BLOCK / 64;
+  for (int64_t x : {std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)), P.total_seeds,
+                    P.chunks * split, (int64_t)P.nq, P.total_kd, (P.total_slots + waves - 1) / waves})
+    key.push_back(launch_size(P, x));
+  key.push_back((int64_t)score_lds(P));
+  key.push_back((int64_t)P.early);
+  for (const Step &S : steps) key.push_back((int64_t)S.fused);
 }
 
 kws_status launch_expand(const Pass &P, const Step &S, hipStream_t s, Profiler &prof) {
@@ -1342,9 +1726,27 @@ kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof, const Ste
   KWS_DISPATCH_T(P.T, finish_t<TT>(P, last, s, prof))
 }
 
+kws_status launch_early(const Pass &P, int L, hipStream_t s, Profiler &prof) {
+  if (!P.early || P.nq == 0) return KWS_OK;
+  Timer t(prof, s, KC_EARLY);
+  const int grid = clamp_grid(std::min<int64_t>(((int64_t)P.n + BLOCK - 1) / BLOCK, 4096));
+  const size_t lds = sizeof(int32_t) * (size_t)launch_size(P, P.nq);   // a replay may carry more queries
+  switch (P.T) {
+    case 1: k_early_count<1><<<grid, BLOCK, lds, s>>>(P.dev, L); break;
+    case 2: k_early_count<2><<<grid, BLOCK, lds, s>>>(P.dev, L); break;
+    case 4: k_early_count<4><<<grid, BLOCK, lds, s>>>(P.dev, L); break;
+    case 8: k_early_count<8><<<grid, BLOCK, lds, s>>>(P.dev, L); break;
+    case 16: k_early_count<16><<<grid, BLOCK, lds, s>>>(P.dev, L); break;
+    default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
+  }
+  KWS_TRY(launch_check("early count"));
+  k_early_apply<<<1, BLOCK, 0, s>>>(P.dev, L);
+  return launch_check("early apply");
+}
+
 kws_status launch_export(const Pass &P, uint8_t *out, hipStream_t s) {
   if (P.T != 1) return fail(KWS_EINVAL, "distance export needs a one-word pass");
-  k_export<1><<<clamp_grid(((int64_t)P.n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P, out);
+  k_export<1><<<clamp_grid(((int64_t)P.n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev, out);
   return launch_check("export");
 }
 

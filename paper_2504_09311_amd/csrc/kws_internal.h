@@ -57,7 +57,7 @@ struct HostBuf {
 // ---------------------------------------------------------------- profiling
 enum KernelClass {
   KC_SEED = 0, KC_PUSH, KC_PULL, KC_FINALIZE, KC_SCORE, KC_THRESHOLD, KC_SELECT,
-  KC_FINISH, KC_ANSWER, KC_EXPORT, KC_BUILD,
+  KC_FINISH, KC_ANSWER, KC_EXPORT, KC_BUILD, KC_EARLY,
   // host phases of a batch (wall time): planning and plan upload, kernel
   // enqueue, waiting for the device, unpacking the results
   KC_HOST_PLAN, KC_HOST_LAUNCH, KC_HOST_WAIT, KC_HOST_COLLECT, KC_COUNT
@@ -105,6 +105,7 @@ struct Engine {
   int state_planes = 0;                // distance planes currently allocated
   DevBuf flist, flist_eoff;            // frontier list and in-edge offsets
   DevBuf flags;                        // [2][n] frontier flags (current, next)
+  DevBuf flags_tile;                   // [tiles][n] per-tile flags of a fused pulled level
   // Buffers of one pass in flight. Set 0 serves the synchronous calls; sets
   // 1 and 2 the two batches a caller may have submitted and not collected.
   struct IoSet {
@@ -128,7 +129,7 @@ struct Engine {
 
 // graph-capture cache entry
 struct GraphEntry {
-  std::vector<uint8_t> key;
+  std::vector<int64_t> key;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -150,6 +151,9 @@ struct kws_graph {
   int32_t *hub_v = nullptr, *hub_b = nullptr, *hub_e = nullptr;
   int64_t bin_begin[kws::BIN_COUNT + 1] = {};
   int64_t n_hub = 0;
+  int32_t *hub_vtx = nullptr;                        // distinct vertices of the hub chunks
+  int32_t *zero_vtx = nullptr;                       // vertices without out-edges
+  int64_t n_hubv = 0, n_zero = 0;
   // host mirrors used for planning
   std::vector<int32_t> pre, span;                    // type preorder key and subtree size
   std::vector<int32_t> h_inv_ptr;                    // [n_labels + 1]
@@ -166,6 +170,7 @@ struct kws_graph {
   kws::Profiler prof;
   kws_batch_stats last{};
   std::vector<kws::GraphEntry> graphs;
+  int64_t graph_captures = 0, graph_replays = 0;     // passes captured / replayed in graph mode
   std::map<int64_t, kws::AsyncBatch *> pending;      // submitted, not yet collected batches
   int64_t next_ticket = 1;
   size_t mem_budget = 0;                             // bytes allowed for search state

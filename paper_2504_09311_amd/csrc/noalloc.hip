@@ -13,6 +13,7 @@
 // share each device's one array) and wait for their device work, so the
 // next call never sees a half-written state; every region a call reads
 // before writing is cleared by that call's own kernels.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -39,6 +40,28 @@ struct LaneTablesArg {
   int32_t seed_begin, word, bit;
 };
 
+// Copies up to one blob of bytes, passed by value, into the array (the pass
+// and step descriptors, which the kernels read from device memory).
+struct Blob {
+  uint8_t b[512];
+};
+
+__global__ void k_noalloc_put(const Blob blob, uint8_t *dst, int len) {
+  for (int i = threadIdx.x; i < len; i += blockDim.x) dst[i] = blob.b[i];
+}
+
+kws_status put_bytes(uint8_t *dst, const void *src, size_t bytes, hipStream_t s) {
+  const uint8_t *p = (const uint8_t *)src;
+  for (size_t off = 0; off < bytes; off += sizeof(Blob)) {
+    Blob b;
+    const size_t len = std::min(sizeof(Blob), bytes - off);
+    std::memcpy(b.b, p + off, len);
+    k_noalloc_put<<<1, 256, 0, s>>>(b, dst + off, (int)len);
+    KWS_HIP(hipGetLastError());
+  }
+  return KWS_OK;
+}
+
 __global__ void k_noalloc_tables(const LaneTablesArg t, int D, uint64_t *act, int8_t *lvl, int64_t *seed_off,
                                  int32_t *seed_begin, int32_t *lane_word, int32_t *lane_bit) {
   const int i = threadIdx.x;
@@ -60,7 +83,7 @@ struct Carve {
 
 struct Regions {
   size_t vis, fr0, fr1, nxt, planes, flist, flist_eoff, flags, act, lvl, stats, live, seed_off, seed_begin,
-      lane_word, lane_bit, end;
+      lane_word, lane_bit, pass, steps, end;
 };
 
 Regions layout(int32_t n, int D, int B) {
@@ -83,6 +106,8 @@ Regions layout(int32_t n, int D, int B) {
   r.seed_begin = c.take(4);
   r.lane_word = c.take(4);
   r.lane_bit = c.take(4);
+  r.pass = c.take(sizeof(Pass));
+  r.steps = c.take(sizeof(Step) * (size_t)(D + 1));
   r.end = c.off;
   return r;
 }
@@ -143,6 +168,7 @@ kws_status distances_noalloc(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *d
 
   Pass P;
   std::memset(&P, 0, sizeof(P));
+  P.dev = (const Pass *)(base + R.pass);
   P.n = n;
   P.T = 1;
   P.tiles = 1;
@@ -203,7 +229,10 @@ kws_status distances_noalloc(kws_graph *g, int32_t kw, int32_t d_max, uint8_t *d
     S.st_out = stats + (size_t)(lv + 1) * STAT_WORDS;
     S.live_out = live + (lv + 1);
     S.build_list = S.write_next = lv + 1 < D;
+    S.dev = (const Step *)(base + R.steps) + (lv + 1);
   }
+  KWS_TRY(put_bytes(base + R.pass, &P, sizeof(Pass), s));
+  KWS_TRY(put_bytes(base + R.steps, steps, sizeof(Step) * (size_t)(D + 1), s));
 
   Profiler off;                        // no events: nothing is created or recorded
   KWS_TRY(launch_fill_zero(P.nxt, (size_t)n, s));   // the seeds are OR-ed into a cleared nxt

@@ -13,11 +13,15 @@
 // so one neighbour visit gathers 8*T bytes; a tile is one contiguous slab.
 #pragma once
 
+#include <vector>
+
 #include "kws_internal.h"
 
 namespace kws {
 
 struct Pass {
+  const Pass *dev;                   // where this descriptor lives in device memory (kernels read it there)
+  int32_t graph_mode;                // launch grids depend on the pass shape only (captured graphs replay)
   // sizes
   int32_t n, T, tiles, Wp, B, nq, n_lanes;
   int32_t W;                         // words in use; words W..Wp-1 pad the last tile (no lane, no query)
@@ -30,6 +34,8 @@ struct Pass {
   // graph
   const int32_t *fwd_ptr, *fwd_col, *rev_ptr, *rev_col, *inv_vtx;
   const int32_t *bin_vtx, *hub_v, *hub_b, *hub_e;
+  const int32_t *hub_vtx, *zero_vtx;   // distinct hub vertices; vertices without out-edges
+  int64_t n_hubv, n_zero;
   // state
   uint64_t *vis, *fr0, *fr1, *nxt, *planes;
   int32_t *flist, *flist_eoff;
@@ -60,6 +66,13 @@ struct Pass {
   int32_t *qsel;                     // [nq * 4]: k_eff, s*, need, c_lt
   int4 *work;
   uint64_t *cand;
+  // top-k early termination: per query, complete roots scoring at most the
+  // current level, and the level after which the query stopped, plus one
+  // (0: still running); the plan's lane-activity table [(levels + 2) x Wp],
+  // from which the stopped queries' lanes are cleared
+  int32_t early, D;
+  int32_t *early_cnt, *early_stop;
+  uint64_t *act_tab;
   // results
   int32_t *r_nroots, *r_roots, *r_scores, *r_ecount;
   uint8_t *r_kwdist;
@@ -71,6 +84,7 @@ struct Pass {
 // arrivals get; 0 means the word starts here (vis is reset to the seeds and
 // the distance planes are cleared).
 struct Step {
+  const Step *dev;           // where this descriptor lives in device memory
   const uint64_t *act_exp;   // [Wp] lanes that expand in this step
   const uint64_t *live_in;   // [Wp] lanes whose current frontier is non-empty
   const uint64_t *st_in;     // statistics of the current frontier: (n_f << 32 | m_f), m_u, list counter
@@ -87,6 +101,12 @@ struct Step {
   int32_t write_next;        // write fr_next and live_out
   int32_t clear_planes;      // clear the distance planes when a word starts; otherwise every
                              // word reaches level 2^b for every plane b, where b is stored
+  int32_t fused;             // a pulled level is finalized by the pull itself (every word's
+                             // newlvl >= 1, planes stored at their first level): k_pull_fin for
+                             // the rows, k_fin_list for the hub vertices, k_fin_stats for the
+                             // per-vertex flags and statistics; k_finalize then only runs for
+                             // pushed or empty levels
+  uint8_t *flags_tile;       // [tiles][n] per vertex and tile: bit 0 new lanes, bit 1 lanes still to reach
 };
 
 kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof);
@@ -99,6 +119,15 @@ kws_status launch_finalize(const Pass &P, const Step &S, hipStream_t s, Profiler
 // finalize of that step (the last level of a batched pass).
 kws_status launch_finish(const Pass &P, hipStream_t s, Profiler &prof, const Step *last = nullptr);
 kws_status launch_export(const Pass &P, uint8_t *out, hipStream_t s);
+// Top-k early termination after level L (every level of the pass up to L
+// finalized): queries with at least k complete roots scoring at most L stop,
+// and lanes no running query needs leave the activity table.
+kws_status launch_early(const Pass &P, int L, hipStream_t s, Profiler &prof);
 kws_status launch_fill_zero(uint64_t *p, size_t words, hipStream_t s);
+// Everything the launches of a pass in graph mode depend on: passes with
+// equal keys launch the same kernels with the same grids, LDS sizes and
+// arguments, so one captured graph serves them all (fin_last: the score
+// kernel finalizes the last level).
+void graph_shape_key(const Pass &P, const std::vector<Step> &steps, bool fin_last, std::vector<int64_t> &key);
 
 }  // namespace kws

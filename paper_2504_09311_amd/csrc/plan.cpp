@@ -200,12 +200,29 @@ size_t PlanWriter::add(const void *src, size_t bytes) {
   return off;
 }
 
-kws_status PlanWriter::upload(Engine &E, hipStream_t s) {
+kws_status PlanWriter::prepare(Engine &E) {
+  // grown to a power of two (at least 64 KB), so that batches whose plans
+  // differ a little keep the buffer, and with it the descriptors' device
+  // addresses a captured graph was recorded with
+  size_t cap = (size_t)64 << 10;
+  while (cap < size) cap <<= 1;
+  if (E.io().plan.bytes < size) {
+    KWS_TRY(E.io().h_plan.ensure(cap, "plan (host)"));
+    KWS_TRY(E.io().plan.ensure(cap, "plan"));
+  }
   KWS_TRY(E.io().h_plan.ensure(size, "plan (host)"));
-  KWS_TRY(E.io().plan.ensure(size, "plan"));
+  return KWS_OK;
+}
+
+void PlanWriter::put(Engine &E, size_t off, const void *src, size_t bytes) {
+  std::memcpy(E.io().h_plan.as<uint8_t>() + off, src, bytes);
+}
+
+kws_status PlanWriter::upload(Engine &E, hipStream_t s) {
+  KWS_TRY(prepare(E));
   uint8_t *hp = E.io().h_plan.as<uint8_t>();
   for (const Piece &p : pieces)
-    if (p.bytes) std::memcpy(hp + p.off, p.src, p.bytes);
+    if (p.bytes && p.src) std::memcpy(hp + p.off, p.src, p.bytes);
   KWS_HIP(hipMemcpyAsync(E.io().plan.p, hp, size, hipMemcpyHostToDevice, s));
   return KWS_OK;
 }
@@ -254,6 +271,7 @@ ArenaLayout arena_layout(const QueryTables &Q, size_t extra_bytes, size_t live_w
   Layout l;
   a.extra = l.add(extra_bytes + stats_words * 8);
   a.te = l.add((size_t)Q.nq * 8);
+  a.early = l.add((size_t)Q.nq * 8);     // early-termination counts and stop levels
   a.zero_end = align_up(l.size, 8);
   a.nroots = l.add((size_t)Q.nq * 4);
   a.roots = l.add((size_t)Q.nslots * 4);
@@ -299,6 +317,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.pstride = (size_t)g->n * P.Wp;
   P.fwd_ptr = g->fwd_ptr; P.fwd_col = g->fwd_col; P.rev_ptr = g->rev_ptr; P.rev_col = g->rev_col;
   P.inv_vtx = g->inv_vtx; P.bin_vtx = g->bin_vtx; P.hub_v = g->hub_v; P.hub_b = g->hub_b; P.hub_e = g->hub_e;
+  P.hub_vtx = g->hub_vtx; P.zero_vtx = g->zero_vtx; P.n_hubv = g->n_hubv; P.n_zero = g->n_zero;
   P.vis = E.vis.as<uint64_t>(); P.fr0 = E.fr0.as<uint64_t>(); P.fr1 = E.fr1.as<uint64_t>();
   P.nxt = E.nxt.as<uint64_t>(); P.planes = E.planes.as<uint64_t>();
   P.flist = E.flist.as<int32_t>(); P.flist_eoff = E.flist_eoff.as<int32_t>();
@@ -354,6 +373,8 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.zero1 = (uint64_t *)zr;
   P.zero1_words = (int64_t)(al.z_size / 8);
   P.te = (uint64_t *)(ar + al.te);
+  P.early_cnt = (int32_t *)(ar + al.early);
+  P.early_stop = P.early_cnt + Q.nq;
   P.cand_cnt = (int32_t *)(zr + al.z_ccnt);
   P.work_cnt = (int32_t *)(zr + al.z_wcnt);
   P.hist = (int32_t *)(zr + al.z_hist);

@@ -16,6 +16,8 @@ namespace {
 
 constexpr kws_status PASS_TOO_WIDE = (kws_status)1;   // internal: retry with fewer queries
 
+bool score_finalizes_last(const Pass &P, const std::vector<Step> &steps);
+
 // Device work of one pass: seed, D levels, finish.
 kws_status launch_pass(kws_graph *g, const Pass &P, const std::vector<Step> &steps) {
   hipStream_t s = g->stream;
@@ -25,28 +27,40 @@ kws_status launch_pass(kws_graph *g, const Pass &P, const std::vector<Step> &ste
     KWS_TRY(launch_seed(P, s, g->prof));
     KWS_TRY(launch_finalize(P, steps[0], s, g->prof));
   }
+  if (steps.size() > 1) KWS_TRY(launch_early(P, 0, s, g->prof));
   // With tiles of at most 8 words a score thread holds a vertex's whole
   // tile row, so the score kernel does the last level's finalize (its
   // stores fill whole lines); wider tiles keep the separate pass, where the
   // stores of the merge would be scattered partial lines.
-  const Step *last = nullptr;
+  // With the finalize fused into pulled levels the last level may already
+  // be final when scoring starts, so the score kernel does not merge it.
+  const bool fin_last = score_finalizes_last(P, steps);
   for (size_t i = 1; i < steps.size(); i++) {
     KWS_TRY(launch_expand(P, steps[i], s, g->prof));
-    if (i + 1 < steps.size() || P.T > 8) KWS_TRY(launch_finalize(P, steps[i], s, g->prof));
-    else last = &steps[i];
+    if (i + 1 < steps.size() || !fin_last) KWS_TRY(launch_finalize(P, steps[i], s, g->prof));
+    if (i + 1 < steps.size()) KWS_TRY(launch_early(P, (int)i, s, g->prof));
   }
-  return launch_finish(P, s, g->prof, last);
+  return launch_finish(P, s, g->prof, fin_last ? &steps.back() : nullptr);
 }
 
-// The same work through a hipGraph captured once per pass shape (the key
-// holds every launch argument) and replayed afterwards.
+// Whether the score kernel finalizes the last level (launch_pass decides
+// the same way).
+bool score_finalizes_last(const Pass &P, const std::vector<Step> &steps) {
+  return steps.size() > 1 && P.T <= 8 && !steps.back().fused;
+}
+
+// The same work through a hipGraph captured once per pass shape and
+// replayed for every later pass of that shape. The kernels read the pass
+// and step descriptors from the plan buffer, which each pass uploads before
+// the launch, so the graph holds no per-batch value: its key is the
+// descriptors' device addresses and the launch shape (graph_shape_key).
 kws_status launch_pass_graph(kws_graph *g, const Pass &P, const std::vector<Step> &steps) {
-  std::vector<uint8_t> key(sizeof(Pass) + steps.size() * sizeof(Step));
-  std::memcpy(key.data(), &P, sizeof(Pass));
-  std::memcpy(key.data() + sizeof(Pass), steps.data(), steps.size() * sizeof(Step));
+  std::vector<int64_t> key;
+  graph_shape_key(P, steps, score_finalizes_last(P, steps), key);
   for (auto &e : g->graphs)
     if (e.key == key) {
       KWS_HIP(hipGraphLaunch(e.exec, g->stream));
+      g->graph_replays++;
       return KWS_OK;
     }
   hipGraph_t graph = nullptr;
@@ -67,6 +81,7 @@ kws_status launch_pass_graph(kws_graph *g, const Pass &P, const std::vector<Step
     g->graphs.erase(g->graphs.begin());
   }
   g->graphs.push_back({key, exec});
+  g->graph_captures++;
   KWS_HIP(hipGraphLaunch(exec, g->stream));
   return KWS_OK;
 }
@@ -101,6 +116,14 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
   KWS_TRY(E.flist.ensure(sizeof(int32_t) * (size_t)n, "frontier list"));
   KWS_TRY(E.flist_eoff.ensure(sizeof(int32_t) * (size_t)n, "frontier offsets"));
   KWS_TRY(E.flags.ensure(2 * (size_t)n, "frontier flags"));
+  // Fusing the finalize into pulled levels pays when the pull's per-row
+  // writes are whole 128-byte lines (16-word tiles) and a state array is far
+  // larger than the 256 MB Infinity Cache, where the separate finalize pass
+  // streams from HBM; with smaller state that pass runs from cache and
+  // narrower rows would be scattered partial-line writes.
+  const bool fused = D > 0 && (o.fused_pull > 0 || (o.fused_pull == 0 && T == 16 &&
+                                                    (size_t)n * (size_t)Wp * 8 > ((size_t)512 << 20)));
+  if (fused) KWS_TRY(E.flags_tile.ensure((size_t)n * tiles, "tile flags"));
 
   LaneTables L;
   for (const LaneInfo &li : pk.lanes) L.add(g, li);
@@ -126,15 +149,29 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
   KWS_TRY(E.io().cand.ensure(8 * (size_t)std::max<int64_t>(Q.ncand, 1), "candidates"));
 
   PlanWriter pw;
+  // the descriptors first: their device addresses (which a captured graph
+  // holds) then do not move with the sizes of the batch's tables
+  const size_t o_pass = pw.reserve(sizeof(Pass));
+  const size_t o_steps = pw.reserve(sizeof(Step) * (size_t)(D + 1));
   const LaneOffsets lo = add_lane_tables(pw, L);
   const QueryOffsets qo = add_query_tables(pw, Q);
   const size_t o_act = pw.add(act.data(), act.size() * 8);
   const size_t o_lvl = pw.add(newlvl.data(), newlvl.size());
-  KWS_TRY(pw.upload(E, g->stream));
+  KWS_TRY(pw.prepare(E));
 
+  const bool graph_mode = o.use_graph > 0 && !g->prof.on && !export_only;
   Pass P;
   fill_pass(P, g, E, T, tiles, B, L, lo, Q, qo, al);
   P.W = W;
+  P.dev = pw.dev<Pass>(E, o_pass);
+  P.graph_mode = graph_mode;
+  // top-k early termination, on request: its per-level check reads every
+  // vertex's vis and planes, which on the measured workloads costs more
+  // than the expansion it saves
+  P.D = D;
+  P.act_tab = const_cast<uint64_t *>(pw.dev<uint64_t>(E, o_act));
+  P.early = !export_only && nq > 0 && D > 0 && o.early_stop > 0 &&
+            nq <= 16384;   // per-query counters in LDS (rounded up to a power of two in graph mode)
   uint64_t *stats = (uint64_t *)(E.io().arena.as<uint8_t>() + al.extra);
   uint64_t *live = (uint64_t *)(E.io().zero_region.as<uint8_t>() + al.z_live);
   const uint64_t *act_d = pw.dev<uint64_t>(E, o_act);
@@ -158,8 +195,14 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
     S.st_out = stats + (size_t)(lv + 1) * STAT_WORDS;
     S.live_out = live + (size_t)(lv + 1) * Wp;
     S.build_list = S.write_next = lv + 1 < D;
+    S.fused = lv >= 0 && fused;
+    S.flags_tile = fused ? E.flags_tile.as<uint8_t>() : nullptr;
+    S.dev = pw.dev<Step>(E, o_steps) + (lv + 1);
     steps.push_back(S);
   }
+  pw.put(E, o_pass, &P, sizeof(Pass));
+  pw.put(E, o_steps, steps.data(), sizeof(Step) * steps.size());
+  KWS_TRY(pw.upload(E, g->stream));
 
   if (export_only) {
     DevBuf tmp;
@@ -175,7 +218,7 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
 
   g->prof.host(KC_HOST_PLAN, ms_since(t_phase));
   t_phase = clk::now();
-  if (o.use_graph > 0 && !g->prof.on) KWS_TRY(launch_pass_graph(g, P, steps));
+  if (graph_mode) KWS_TRY(launch_pass_graph(g, P, steps));
   else KWS_TRY(launch_pass(g, P, steps));
   KWS_HIP(hipMemcpyAsync(E.io().h_arena.p, E.io().arena.p, al.size, hipMemcpyDeviceToHost, g->stream));
   if (!E.io().done) KWS_HIP(hipEventCreateWithFlags(&E.io().done, hipEventDisableTiming));
@@ -193,6 +236,8 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
   rec.D = D;
   rec.direction = o.direction;
   rec.alpha = o.alpha;
+  rec.early = P.early != 0;
+  rec.fused = fused;
   return KWS_OK;
 }
 
@@ -215,6 +260,15 @@ kws_status finish_pass(kws_graph *g, PassRecord &rec, kws_result *out, FlatOut *
 
   const uint64_t *h_stats = (const uint64_t *)(io.h_arena.as<uint8_t>() + rec.al.extra);
   kws_batch_stats &bs = g->last;
+  bs.fused_pull = rec.fused ? 1 : 0;
+  if (rec.early) {
+    const int32_t *h_stop = (const int32_t *)(io.h_arena.as<uint8_t>() + rec.al.early) + nq;
+    for (int i = 0; i < nq; i++)
+      if (h_stop[i] > 0) {
+        bs.early_stopped += 1;
+        bs.levels_skipped += rec.qp[i]->dmax - (h_stop[i] - 1);
+      }
+  }
   bs.queries += nq;
   bs.lanes += rec.lanes;
   bs.lane_slots += rec.lane_slots;
@@ -263,6 +317,8 @@ void default_options(kws_options *o) {
   o->use_graph = 0;
   o->share_lanes = 1;
   o->count_te = 0;
+  o->fused_pull = 0;
+  o->early_stop = 0;
 }
 
 namespace {

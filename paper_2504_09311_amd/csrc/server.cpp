@@ -189,10 +189,12 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
   const QueryOffsets qo = add_query_tables(pw, Q);
   const size_t o_exp = pw.add(act_exp.data(), Wp * 8), o_new = pw.add(act_new.data(), Wp * 8),
                o_nn = pw.add(act_nn.data(), Wp * 8), o_lvl = pw.add(newlvl.data(), Wp);
-  KWS_TRY(pw.upload(E, s->stream));
+  const size_t o_pass = pw.reserve(sizeof(Pass)), o_step = pw.reserve(sizeof(Step));
+  KWS_TRY(pw.prepare(E));
 
   Pass P;
   fill_pass(P, g, E, T, tiles, s->B, L, lo, Q, qo, al);
+  P.dev = pw.dev<Pass>(E, o_pass);
   P.W = top + 1;
   P.pstride = (size_t)n * s->tiles_alloc * T;   // planes are laid out for every slot
   const int par = (int)(s->step_no & 1);
@@ -217,6 +219,10 @@ kws_status device_step(kws_server *s, std::vector<std::pair<uint64_t, kws_result
   S.build_list = 1;
   S.write_next = 1;
   S.clear_planes = 1;   // a slot's word stops at its own d_max
+  S.dev = pw.dev<Step>(E, o_step);
+  pw.put(E, o_pass, &P, sizeof(Pass));
+  pw.put(E, o_step, &S, sizeof(Step));
+  KWS_TRY(pw.upload(E, s->stream));
   // the step's output statistics are cleared with the counters
   KWS_HIP(hipMemsetAsync(S.st_out, 0, STAT_WORDS * sizeof(uint64_t), s->stream));
   KWS_TRY(launch_seed(P, s->stream, s->prof));

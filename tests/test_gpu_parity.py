@@ -67,9 +67,10 @@ def test_tiny_random(K, block):
         for i, q in enumerate(qs):
             assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"tiny {seed} plain {i}")
         for direction in (0, 1, 2):
+            fused = 1 if (seed + direction) % 2 else -1
             G.set_options(direction=direction, tile_words=[1, 2, 4, 8, 16][seed % 5],
-                          share_lanes=1 if seed % 2 else -1, seed_mode=(seed + direction) % 3)
-            assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction}")
+                          share_lanes=1 if seed % 2 else -1, seed_mode=(seed + direction) % 3, fused_pull=fused)
+            assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction} fused {fused}")
         assert_all_same(G.search_batch_each(qs), want, f"tiny {seed} batch (per-query results)")
         G.close()
 
@@ -89,7 +90,7 @@ def test_tiny_batch_of_many_words(K):
         for share in (1, -1):
             for sm in (1, 2):
                 say("many words", tw, share, sm)
-                G.set_options(tile_words=tw, share_lanes=share, seed_mode=sm)
+                G.set_options(tile_words=tw, share_lanes=share, seed_mode=sm, fused_pull=share)
                 assert_all_same(G.search_batch(qs), want, f"many tw {tw} share {share} seed {sm}")
     G.close()
 
@@ -177,6 +178,9 @@ def test_rmat14_options_grid(K, rmat14):
             say("rmat14", tw, direction)
             G.set_options(direction=direction, tile_words=tw)
             assert_all_same(G.search_batch(qs), want, f"rmat14 tw {tw} dir {direction}")
+        # pulled levels with the separate finalize pass
+        G.set_options(direction=2, tile_words=tw, fused_pull=-1)
+        assert_all_same(G.search_batch(qs), want, f"rmat14 tw {tw} pull, unfused")
     G.set_options(share_lanes=-1)
     assert_all_same(G.search_batch(qs), want, "rmat14 no sharing")
     for sm in (1, 2):
@@ -196,12 +200,60 @@ def test_rmat14_hierarchy(K):
     for direction in (0, 1, 2):
         for sm in (0, 1, 2):
             say("rmat14 hier", direction, sm)
-            G.set_options(direction=direction, seed_mode=sm)
+            G.set_options(direction=direction, seed_mode=sm, fused_pull=-1 if sm == 1 else 1)
             assert_all_same(G.search_batch(qs), want, f"hier dir {direction} seed {sm}")
     G.set_options()
     for i in range(0, 64, 9):
         assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"hier plain {i}")
     G.close()
+
+
+def test_early_stop_is_exact(K, chunglu, rmat14):
+    """Top-k early termination forced on: every root, score, keyword
+    distance and answer edge equals the oracle's, for the plain path and for
+    batches (fused and unfused pulls, graph replay); te is left out, since a
+    query that stops early scans fewer edges. Queries do stop early."""
+    stopped = 0
+    cases = [("chunglu", chunglu[0], chunglu[1], chunglu[2], workloads.chunglu10k_queries(101)),
+             ("rmat14", rmat14[0], rmat14[1], rmat14[2],
+              workloads.rmat_flat_queries(96, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=3))]
+    gh, leaves = workloads.rmat_hier(14, cfg=4)
+    cases.append(("rmat14 hier", gh, oracle.Oracle(gh), None, workloads.rmat_hier_queries(gh.type_parent, leaves,
+                                                                                             64, cfg=4)))
+    for name, g, o, G, qs in cases:
+        own = G is None
+        if own:
+            G = K.Graph.from_synth(g)
+        want = oracle_results(o, qs)
+        for fused in (1, -1):
+            for graph in (0, 1):
+                say("early stop", name, fused, graph)
+                G.set_options(early_stop=1, fused_pull=fused, use_graph=graph, count_te=0)
+                assert_all_same(G.search_batch(qs), want, f"{name} early batch fused {fused} graph {graph}", te=False)
+                stopped += G.last_batch_stats().early_stopped
+        for i in range(0, len(qs), 5):
+            G.set_options(early_stop=1, count_te=0)
+            assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"{name} early plain {i}", te=False)
+            stopped += G.last_batch_stats().early_stopped
+        G.set_options()
+        if own:
+            G.close()
+    say("queries stopped early:", stopped)
+    assert stopped > 0
+
+
+def test_early_stop_tiny(K):
+    for seed in range(0, 200, 3):
+        g = tiny.random_graph(seed)
+        qs = tiny.random_queries(g, seed, 6)
+        o = oracle.Oracle(g)
+        want = [o.search(q.kw, q.d_max, q.k) for q in qs]
+        G = K.Graph.from_synth(g)
+        G.set_options(early_stop=1, count_te=0, tile_words=[1, 2, 4, 8, 16][seed % 5], fused_pull=1 - 2 * (seed % 2))
+        assert_all_same(G.search_batch(qs), want, f"tiny {seed} early batch", te=False)
+        for i, q in enumerate(qs):
+            assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"tiny {seed} early plain {i}", te=False)
+        G.close()
 
 
 @pytest.fixture(scope="module")
@@ -226,10 +278,10 @@ def test_rmat20_batch256(K, rmat20):
     g, _, o, G = rmat20
     qs = workloads.rmat_flat_queries(256, 2, 8, [2, 3, 4], 20, cfg=2, qcfg=3)
     want = oracle_results(o, qs)
-    for direction in (0, 2):
-        say("rmat20 batch256", direction)
-        G.set_options(direction=direction)
-        assert_all_same(G.search_batch(qs), want, f"rmat20 batch256 dir {direction}")
+    for direction, fused in ((0, 1), (2, 1), (2, -1)):
+        say("rmat20 batch256", direction, fused)
+        G.set_options(direction=direction, fused_pull=fused)
+        assert_all_same(G.search_batch(qs), want, f"rmat20 batch256 dir {direction} fused {fused}")
     G.set_options()
 
 

@@ -124,6 +124,37 @@ def test_graph_replay_matches(K, rmat14):
     G.set_options()
 
 
+def test_graph_replays_across_batches(K, rmat14):
+    """Different batches of one shape (48 queries of 4 keywords, d_max 3,
+    k 20) run through one captured graph: the capture counter moves once,
+    the replay counter once per later batch, and every answer equals the
+    oracle's. The pipelined path (two plan buffers) captures once per buffer."""
+    g, o, _ = rmat14
+    from synth import gen
+    G = K.Graph.from_synth(g)
+    # no lane sharing: 16 four-keyword queries fill a word, so every batch has 3 words
+    G.set_options(use_graph=1, seed_mode=2, share_lanes=-1)
+    batches = [gen.queries(48, g.n_labels, 1.0, 4, 4, [3], 20, 0x5EED0102, 900 + i) for i in range(6)]
+    wants = [oracle_results(o, qs) for qs in batches]
+    assert len({tuple(tuple(q.kw) for q in qs) for qs in batches}) == 6      # six different batches
+    i0 = G.info()
+    for i, (qs, want) in enumerate(zip(batches, wants)):
+        say("replay batch", i)
+        assert_all_same(G.search_batch(qs), want, f"graph batch {i}")
+    i1 = G.info()
+    assert (i1.graph_captures - i0.graph_captures, i1.graph_replays - i0.graph_replays) == (1, 5)
+    # pipelined: submit the next batch before collecting the previous one
+    t = G.search_batch_submit(batches[0])
+    for i in range(1, 7):
+        nxt = G.search_batch_submit(batches[i % 6]) if i < 6 else None
+        got = K.Graph.results_of(G.search_batch_collect(t), len(batches[i - 1]))
+        assert_all_same(got, wants[i - 1], f"pipelined graph batch {i - 1}")
+        t = nxt
+    i2 = G.info()
+    assert (i2.graph_captures - i1.graph_captures, i2.graph_replays - i1.graph_replays) == (2, 4)
+    G.close()
+
+
 def test_caller_stream(K, rmat14):
     """Work on a stream the caller created through the library's own HIP runtime."""
     import ctypes
