@@ -963,44 +963,39 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
           const int j = tile * T + h0 + w;
           const int qb = __builtin_amdgcn_readfirstlane(wqp[j]), qe = __builtin_amdgcn_readfirstlane(wqp[j + 1]);
           if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
-          // the masks of four queries are read before any of them is tested
-          for (int q0 = qb; q0 < qe; q0 += 4) {
-            uint64_t m4[4];
+          // a plain loop over the word's queries, the next mask loaded ahead;
+          // invalid lanes miss every lane, so they are never roots. Planes
+          // past P.B hold zero in registers and every d_max is below 2^P.B,
+          // so no plane needs a bound check here.
+          const uint64_t miss = valid ? ~vis[w] : ~0ull;
+          uint64_t m_next = L ? s_qm[qb] : P.q_mask[P.word_q[qb]];
+          for (int qi = qb; qi < qe; qi++) {
+            const uint64_t m = m_next;
+            if (qi + 1 < qe) m_next = L ? s_qm[qi + 1] : P.q_mask[P.word_q[qi + 1]];
+            const bool root = (m & miss) == 0;
+            if (TE) {
+              const int q = L ? s_qx[qi] : P.word_q[qi];
+              const int dq = L ? s_qd[qi] : P.q_dmax[q];
+              const uint64_t x = vis[w] & m;
+              uint64_t eq = x;
 #pragma unroll
-            for (int k4 = 0; k4 < 4; k4++)
-              m4[k4] = q0 + k4 < qe ? (L ? s_qm[q0 + k4] : P.q_mask[P.word_q[q0 + k4]]) : ~0ull;
-#pragma unroll
-            for (int k4 = 0; k4 < 4; k4++) {
-              const int qi = q0 + k4;
-              if (qi >= qe) break;
-              const uint64_t m = m4[k4];
-              const bool root = valid && (m & ~vis[w]) == 0;
-              if (TE) {
-                const int q = L ? s_qx[qi] : P.word_q[qi];
-                const int dq = L ? s_qd[qi] : P.q_dmax[q];
-                const uint64_t x = vis[w] & m;
-                uint64_t eq = x;
-#pragma unroll
-                for (int b = 0; b < PB; b++)
-                  if (b < P.B) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
-                uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
-                if (__ballot(t != 0)) {
-                  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-                  if (lane == 0) {
-                    if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
-                    else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
-                  }
+              for (int b = 0; b < PB; b++) eq &= ((dq >> b) & 1) ? pl[b][w] : ~pl[b][w];
+              uint64_t t = (uint64_t)(__popcll(x) - __popcll(eq)) * indeg;
+              if (__ballot(t != 0)) {
+                for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+                if (lane == 0) {
+                  if (L) atomicAdd((unsigned long long *)&s_te[qi], (unsigned long long)t);
+                  else atomicAdd((unsigned long long *)&P.te[q], (unsigned long long)t);
                 }
               }
-              if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
-              int sc = __popcll(pl[0][w] & m);
+            }
+            if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
+            int sc = 0;
 #pragma unroll
-              for (int b = 1; b < PB; b++)
-                if (b < P.B) sc += __popcll(pl[b][w] & m) << b;
-              if (root) {
-                if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
-                else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
-              }
+            for (int b = 0; b < PB; b++) sc += __popcll(pl[b][w] & m) << b;
+            if (root) {
+              if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
+              else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
             }
           }
         }
