@@ -410,6 +410,8 @@ def main():
                     help="pulled levels finalize inside the pull: 0 the library's choice, 1 always, -1 never")
     ap.add_argument("--early-stop", type=int, default=0,
                     help="top-k early termination: 1 on, 0 or -1 off (the library's default)")
+    ap.add_argument("--seed-table", type=int, default=0,
+                    help="vertex seeding from a per-batch type-row table: 0 the library's choice, 1 always, -1 never")
     ap.add_argument("--pipeline", type=int, default=1,
                     help="1: submit batch i+1 before collecting batch i (host work overlaps the device)")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
@@ -456,7 +458,7 @@ def main():
     G = K.Graph.from_synth(g)
     load_s = time.perf_counter() - t0
     G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words, use_graph=args.graph,
-                  count_te=1, fused_pull=args.fused_pull, early_stop=args.early_stop)
+                  count_te=1, fused_pull=args.fused_pull, early_stop=args.early_stop, seed_table=args.seed_table)
     log("graph loaded in %.2f s" % load_s)
     tuned = None
     if args.autotune:
@@ -470,11 +472,12 @@ def main():
         if args.autotune:
             G.set_options(direction=o.direction, alpha=o.alpha, tile_words=o.tile_words,
                           use_graph=o.use_graph if use_graph is None else use_graph, share_lanes=o.share_lanes,
-                          count_te=on, seed_mode=o.seed_mode, fused_pull=o.fused_pull, early_stop=o.early_stop)
+                          count_te=on, seed_mode=o.seed_mode, fused_pull=o.fused_pull, early_stop=o.early_stop,
+                          seed_table=o.seed_table)
         else:
             G.set_options(direction=args.direction, alpha=args.alpha, tile_words=args.tile_words,
                           use_graph=args.graph if use_graph is None else use_graph, count_te=on,
-                          fused_pull=args.fused_pull, early_stop=args.early_stop)
+                          fused_pull=args.fused_pull, early_stop=args.early_stop, seed_table=args.seed_table)
 
     set_count_te(1)
 

@@ -217,6 +217,13 @@ typedef struct {
                             only the levels expanded). 1: on; 0 (default) or -1: off. The check
                             after each level reads every vertex's vis and distance planes, which on
                             the measured workloads costs more than the expansion it saves */
+  int32_t seed_table;    /* seeding by vertex (seed_mode 2, or its auto choice) from a per-batch table
+                            of n_labels rows of words: row t holds the lanes whose keyword is t or an
+                            ancestor of t, built by one walk per type, so a vertex ORs the rows of its
+                            labels instead of walking and hashing each label's ancestors. 0 (default):
+                            when twice the label count is at most both the vertex count and the
+                            (vertex, label) pair count; 1: always; -1: never. The table takes
+                            8 * n_labels bytes per word of the batch */
 } kws_options;
 kws_status kws_set_options(kws_graph *g, const kws_options *opt);
 kws_status kws_get_options(kws_graph *g, kws_options *opt);
@@ -319,6 +326,7 @@ typedef struct {
   int32_t fused_pull;      /* 1 if pulled levels were finalized inside the pull (fused_pull) */
   int64_t early_stopped;   /* queries that stopped before their d_max (early_stop) */
   int64_t levels_skipped;  /* sum over those queries of d_max minus the level they stopped after */
+  int32_t seed_table;      /* 1 if a pass seeded from the type-row table (seed_table) */
 } kws_batch_stats;
 kws_status kws_last_batch_stats(kws_graph *g, kws_batch_stats *st);
 

@@ -138,7 +138,7 @@ void Engine::IoSet::release() {
 }
 
 void Engine::release() {
-  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags, &flags_tile};
+  DevBuf *d[] = {&vis, &fr0, &fr1, &nxt, &planes, &flist, &flist_eoff, &flags, &flags_tile, &type_rows};
   for (DevBuf *b : d) b->release();
   for (IoSet &x : ios) x.release();
   state_words = 0;
@@ -382,6 +382,8 @@ kws_status kws_set_options(kws_graph *g, const kws_options *opt) {
   o.fused_pull = opt->fused_pull;
   if (opt->early_stop < -1 || opt->early_stop > 1) return kws::fail(KWS_EINVAL, "early_stop must be -1, 0 or 1");
   o.early_stop = opt->early_stop;
+  if (opt->seed_table < -1 || opt->seed_table > 1) return kws::fail(KWS_EINVAL, "seed_table must be -1, 0 or 1");
+  o.seed_table = opt->seed_table;
   std::lock_guard<std::mutex> lk(g->mu);
   g->opt = o;
   return KWS_OK;

@@ -96,7 +96,7 @@ struct PassRecord {
   ArenaLayout al;
   bool te_counted = false;
   int nq = 0, lanes = 0, lane_slots = 0, W = 0, Wp = 0, tiles = 0, T = 0, D = 0, direction = 0;
-  bool early = false, fused = false;
+  bool early = false, fused = false, seed_table = false;
   float alpha = 0.f;
 };
 
@@ -119,6 +119,11 @@ QueryOffsets add_query_tables(PlanWriter &pw, const QueryTables &Q);
 // Offsets of the lane seed tables inside the plan buffer.
 struct LaneOffsets { size_t seed_off, seed_begin, word, bit, h_key, h_beg, h_cnt, e_word, e_mask; };
 LaneOffsets add_lane_tables(PlanWriter &pw, LaneTables &L);
+
+// Seeding by vertex for this batch's lanes (seed_mode, or its auto rule).
+bool seeds_by_vertex(const kws_graph *g, const LaneTables &L);
+// Whether seeding by vertex goes through the type-row table (seed_table).
+bool type_rows_wanted(const kws_graph *g);
 
 // Fills the parts of a Pass common to batch and serving (graph, state,
 // lane and query tables, arena, counters); the caller sets the options.

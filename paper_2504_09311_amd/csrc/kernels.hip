@@ -104,13 +104,74 @@ __global__ __launch_bounds__(BLOCK) void k_seed(const Pass *__restrict__ Pp) {
   }
 }
 
-// ---- seeding by vertex: a block takes VB vertices at a time and gives each
-// BLOCK / VB threads; they walk the vertex's labels and (with a type
-// hierarchy) their ancestors, look each type up in the pass's keyword hash
-// and OR the lane masks of its entries into an LDS row of Wp words per
-// vertex (the threads of a vertex split the entries). The rows are then
-// written to nxt tile by tile, so the stores follow the [tile][vertex][T]
-// layout instead of scattering one word per (vertex, keyword).
+// ---- seeding by vertex: the lanes a vertex starts are those whose keyword
+// is one of its labels or (with a type hierarchy) an ancestor of one.
+//
+// type_walk: the threads of one row (SUB of them, this one `sub`) walk the
+// type t and its ancestors, look each up in the pass's keyword hash and OR
+// the lane masks of its entries into the LDS row (they split the entries).
+__device__ __forceinline__ void type_walk(const Pass &P, int32_t t, uint64_t *row, int sub, int SUB) {
+  const uint32_t hmask = (uint32_t)P.hcap - 1;
+  for (; t >= 0; t = P.tparent ? P.tparent[t] : -1) {
+    uint32_t h = ((uint32_t)t * 2654435761u) & hmask;
+    int32_t key;
+    while ((key = P.h_key[h]) != t && key != -1) h = (h + 1) & hmask;
+    if (key != t) continue;
+    const int32_t e0 = P.h_beg[h], e1 = e0 + P.h_cnt[h];
+    for (int32_t e = e0 + sub; e < e1; e += SUB)
+      atomicOr((unsigned long long *)&row[P.e_word[e]], (unsigned long long)P.e_mask[e]);
+  }
+}
+
+// k_type_rows: with a type-row table, the walk runs once per type instead of
+// once per (vertex, label): row t of the table ([n_types][Wp] words) holds
+// the lanes type t starts, VB types per block round as in the seeding below.
+__global__ __launch_bounds__(BLOCK) void k_type_rows(const Pass *__restrict__ Pp) {
+  const Pass &P = *Pp;
+  extern __shared__ uint64_t s_rows[];   // [VB][Wp + 1]
+  const int tid = threadIdx.x, VB = P.seed_vb, SUB = BLOCK / VB, RS = P.Wp + 1;
+  const int vl = tid / SUB, sub = tid % SUB;
+  for (int64_t t0 = (int64_t)blockIdx.x * VB; t0 < P.n_types; t0 += (int64_t)gridDim.x * VB) {
+    for (int i = tid; i < VB * RS; i += BLOCK) s_rows[i] = 0;
+    __syncthreads();
+    if (t0 + vl < P.n_types) type_walk(P, (int32_t)(t0 + vl), s_rows + (size_t)vl * RS, sub, SUB);
+    __syncthreads();
+    const int nt = (int)min((int64_t)VB, (int64_t)P.n_types - t0);
+    for (int i = tid; i < nt * P.Wp; i += BLOCK) {
+      const int u = i / P.Wp, j = i - u * P.Wp;
+      P.type_rows[(size_t)(t0 + u) * P.Wp + j] = s_rows[(size_t)u * RS + j];
+    }
+    __syncthreads();
+  }
+}
+
+// seed_rows: the LDS rows of the VB vertices from v0 on, either from the
+// type-row table (every (vertex, word) one thread, OR over the vertex's
+// labels; a wavefront reads whole table rows) or by walking each label.
+__device__ __forceinline__ void seed_rows(const Pass &P, int64_t v0, uint64_t *s_rows, int tid, int VB, int RS) {
+  if (P.type_rows) {
+    const int nv = (int)min((int64_t)VB, (int64_t)P.n - v0);
+    for (int i = tid; i < nv * P.W; i += BLOCK) {
+      const int u = i / P.W, j = i - u * P.W;
+      const int32_t a = P.lab_ptr[v0 + u], b = P.lab_ptr[v0 + u + 1];
+      uint64_t m = 0;
+      for (int32_t l = a; l < b; l++) m |= P.type_rows[(size_t)P.lab[l] * P.Wp + j];
+      s_rows[(size_t)u * RS + j] = m;
+    }
+    return;
+  }
+  const int SUB = BLOCK / VB, vl = tid / SUB, sub = tid % SUB;
+  const int64_t v = v0 + vl;
+  if (v < P.n) {
+    const int32_t a = P.lab_ptr[v], b = P.lab_ptr[v + 1];
+    for (int32_t i = a; i < b; i++) type_walk(P, P.lab[i], s_rows + (size_t)vl * RS, sub, SUB);
+  }
+}
+
+// k_seed_vertex: a block takes VB vertices at a time and builds their rows of
+// Wp words in LDS (seed_rows). The rows are then written to nxt tile by
+// tile, so the stores follow the [tile][vertex][T] layout instead of
+// scattering one word per (vertex, keyword).
 template <int T>
 __global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass *__restrict__ Pp) {
   const Pass &P = *Pp;
@@ -119,28 +180,11 @@ __global__ __launch_bounds__(BLOCK) void k_seed_vertex(const Pass *__restrict__ 
   for (int64_t i = gid; i < P.zero0_words; i += gsz) P.zero0[i] = 0;
   for (int64_t i = gid; i < P.zero1_words; i += gsz) P.zero1[i] = 0;
   for (int64_t i = gid; i < P.zero2_words; i += gsz) P.zero2[i] = 0;
-  const int tid = threadIdx.x, VB = P.seed_vb, SUB = BLOCK / VB, RS = P.Wp + 1;
-  const int vl = tid / SUB, sub = tid % SUB;
-  const uint32_t hmask = (uint32_t)P.hcap - 1;
+  const int tid = threadIdx.x, VB = P.seed_vb, RS = P.Wp + 1;
   for (int64_t v0 = (int64_t)blockIdx.x * VB; v0 < P.n; v0 += (int64_t)gridDim.x * VB) {
     for (int i = tid; i < VB * RS; i += BLOCK) s_rows[i] = 0;
     __syncthreads();
-    const int64_t v = v0 + vl;
-    if (v < P.n) {
-      uint64_t *row = s_rows + (size_t)vl * RS;
-      const int32_t a = P.lab_ptr[v], b = P.lab_ptr[v + 1];
-      for (int32_t i = a; i < b; i++) {
-        for (int32_t t = P.lab[i]; t >= 0; t = P.tparent ? P.tparent[t] : -1) {
-          uint32_t h = ((uint32_t)t * 2654435761u) & hmask;
-          int32_t key;
-          while ((key = P.h_key[h]) != t && key != -1) h = (h + 1) & hmask;
-          if (key != t) continue;
-          const int32_t e0 = P.h_beg[h], e1 = e0 + P.h_cnt[h];
-          for (int32_t e = e0 + sub; e < e1; e += SUB)
-            atomicOr((unsigned long long *)&row[P.e_word[e]], (unsigned long long)P.e_mask[e]);
-        }
-      }
-    }
+    seed_rows(P, v0, s_rows, tid, VB, RS);
     __syncthreads();
     const int nv = (int)min((int64_t)VB, (int64_t)P.n - v0);
     for (int i = tid; i < P.tiles * VB * T; i += BLOCK) {
@@ -178,30 +222,15 @@ __global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass *__restrict__ 
   uint64_t *s_live = s_rows + (size_t)VB * RS;
   uint32_t *s_vf = (uint32_t *)(s_live + P.Wp);
   const int vl = tid / SUB, sub = tid % SUB;
-  const uint32_t hmask = (uint32_t)P.hcap - 1;
   uint64_t nf_acc = 0, mf_acc = 0, mu_acc = 0;
   for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
   for (int64_t v0 = (int64_t)blockIdx.x * VB; v0 < P.n; v0 += (int64_t)gridDim.x * VB) {
     for (int i = tid; i < VB * RS; i += BLOCK) s_rows[i] = 0;
     for (int i = tid; i < VB; i += BLOCK) s_vf[i] = 0;
     __syncthreads();
-    const int64_t v = v0 + vl;
-    if (v < P.n) {
-      uint64_t *row = s_rows + (size_t)vl * RS;
-      const int32_t a = P.lab_ptr[v], b = P.lab_ptr[v + 1];
-      for (int32_t i = a; i < b; i++) {
-        for (int32_t t = P.lab[i]; t >= 0; t = P.tparent ? P.tparent[t] : -1) {
-          uint32_t h = ((uint32_t)t * 2654435761u) & hmask;
-          int32_t key;
-          while ((key = P.h_key[h]) != t && key != -1) h = (h + 1) & hmask;
-          if (key != t) continue;
-          const int32_t e0 = P.h_beg[h], e1 = e0 + P.h_cnt[h];
-          for (int32_t e = e0 + sub; e < e1; e += SUB)
-            atomicOr((unsigned long long *)&row[P.e_word[e]], (unsigned long long)P.e_mask[e]);
-        }
-      }
-    }
+    seed_rows(P, v0, s_rows, tid, VB, RS);
     __syncthreads();
+    const int64_t v = v0 + vl;
     const int nv = (int)min((int64_t)VB, (int64_t)P.n - v0);
     // per vertex: bit 0 any frontier lane, bit 1 a lane still to reach at level 1
     if (vl < nv) {
@@ -1638,6 +1667,14 @@ kws_status finish_t(const Pass &P, const Step *last, hipStream_t s, Profiler &pr
 
 }  // namespace
 
+// the type-row table of a pass, before its seeding kernel
+void launch_type_rows(const Pass &P, hipStream_t s) {
+  if (!P.type_rows || P.n_types <= 0) return;
+  const int64_t blocks = (P.n_types + P.seed_vb - 1) / P.seed_vb;
+  const size_t lds = sizeof(uint64_t) * (size_t)P.seed_vb * (size_t)(P.Wp + 1);
+  k_type_rows<<<clamp_grid(std::min<int64_t>(blocks, 4096)), BLOCK, lds, s>>>(P.dev);
+}
+
 kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
   const int64_t zwords = launch_size(P, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
   const int64_t items = std::max<int64_t>(P.seed_by_vertex ? P.n : launch_size(P, P.total_seeds), zwords);
@@ -1647,6 +1684,7 @@ kws_status launch_seed(const Pass &P, hipStream_t s, Profiler &prof) {
     const int64_t zblocks = (zwords + BLOCK - 1) / BLOCK;
     const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(std::min<int64_t>(vblocks, 4096), zblocks), 65535));
     const size_t lds = sizeof(uint64_t) * (size_t)P.seed_vb * (size_t)(P.Wp + 1);
+    launch_type_rows(P, s);
     switch (P.T) {
       case 1: k_seed_vertex<1><<<grid, BLOCK, lds, s>>>(P.dev); break;
       case 2: k_seed_vertex<2><<<grid, BLOCK, lds, s>>>(P.dev); break;
@@ -1675,6 +1713,7 @@ kws_status launch_seed_level0(const Pass &P, const Step &S, hipStream_t s, Profi
   Timer t(prof, s, KC_SEED);
   const int64_t zwords = launch_size(P, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
   if (zwords > 0) k_zero_pass<<<clamp_grid((zwords + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev);
+  launch_type_rows(P, s);
   const int64_t vblocks = ((int64_t)P.n + P.seed_vb - 1) / P.seed_vb;
   const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(vblocks, 1), 4096));
   const size_t lds = sizeof(uint64_t) * ((size_t)P.seed_vb * (size_t)(P.Wp + 1) + (size_t)P.Wp) +
@@ -1698,6 +1737,7 @@ void graph_shape_key(const Pass &P, const std::vector<Step> &steps, bool fin_las
   key.push_back(steps.empty() ? 0 : (int64_t)(uintptr_t)steps[0].dev);
   for (int64_t x : {(int64_t)P.T, (int64_t)P.tiles, (int64_t)P.Wp, (int64_t)P.B, (int64_t)P.n,
                     (int64_t)P.seed_by_vertex, (int64_t)P.seed_vb, (int64_t)P.hist_lds, (int64_t)P.count_te,
+                    (int64_t)(P.type_rows != nullptr), P.n_types,
                     (int64_t)fin_last, (int64_t)steps.size(), (int64_t)(P.nq == 0)})
     key.push_back(x);
   const int64_t split = (P.CH + BLOCK - 1) / BLOCK, waves = BLOCK / 64;

@@ -106,6 +106,7 @@ struct Engine {
   DevBuf flist, flist_eoff;            // frontier list and in-edge offsets
   DevBuf flags;                        // [2][n] frontier flags (current, next)
   DevBuf flags_tile;                   // [tiles][n] per-tile flags of a fused pulled level
+  DevBuf type_rows;                    // [n_labels][Wp] lanes each type starts (table seeding)
   // Buffers of one pass in flight. Set 0 serves the synchronous calls; sets
   // 1 and 2 the two batches a caller may have submitted and not collected.
   struct IoSet {

@@ -46,6 +46,10 @@ struct Pass {
   const int32_t *lab_ptr, *lab, *tparent;
   const int32_t *h_key, *h_beg, *h_cnt, *e_word;
   const uint64_t *e_mask;
+  // optional type-row table [n_types][Wp]: the lanes each type starts, built
+  // from the hash once per pass (k_type_rows); null: walk per vertex label
+  uint64_t *type_rows;
+  int64_t n_types;
   const int64_t *lane_seed_off;      // [n_lanes + 1]
   const int32_t *lane_seed_begin;    // [n_lanes]
   const int32_t *lane_word, *lane_bit;

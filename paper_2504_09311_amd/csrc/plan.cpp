@@ -290,6 +290,21 @@ ArenaLayout arena_layout(const QueryTables &Q, size_t extra_bytes, size_t live_w
   return a;
 }
 
+// seed by vertex when scattering would cost more random atomics than one
+// pass over the vertices and their labels
+bool seeds_by_vertex(const kws_graph *g, const LaneTables &L) {
+  const int mode = g->opt.seed_mode;
+  const int64_t lab_total = g->h_lab_total;
+  return L.n() > 0 && (mode == 2 || (mode == 0 && L.seed_off.back() > (int64_t)g->n + lab_total * (1 + g->type_depth)));
+}
+
+// the table pays when its walks (one per type) are few against the walks it
+// replaces (one per vertex label), and it stays small against a state array
+bool type_rows_wanted(const kws_graph *g) {
+  const int o = g->opt.seed_table;
+  return o > 0 || (o == 0 && 2 * (int64_t)g->n_labels <= std::min<int64_t>(g->n, g->h_lab_total));
+}
+
 void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const LaneTables &L,
                const LaneOffsets &lo, const QueryTables &Q, const QueryOffsets &qo, const ArenaLayout &al) {
   std::memset(&P, 0, sizeof(P));
@@ -335,12 +350,14 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.lab_ptr = g->lab_ptr;
   P.lab = g->lab;
   P.tparent = g->tparent;
-  // seed by vertex when scattering would cost more random atomics than one
-  // pass over the vertices and their labels
-  const int64_t lab_total = g->h_lab_total;
-  const int mode = g->opt.seed_mode;
-  P.seed_by_vertex = L.n() > 0 && (mode == 2 || (mode == 0 && P.total_seeds > (int64_t)g->n + lab_total * (1 + g->type_depth)));
+  P.seed_by_vertex = seeds_by_vertex(g, L);
   if (P.seed_by_vertex) P.total_seeds = 0;
+  // the type-row table, when wanted and the caller has sized it for Wp
+  const size_t tr_bytes = (size_t)g->n_labels * (size_t)P.Wp * 8;
+  if (P.seed_by_vertex && type_rows_wanted(g) && E.type_rows.p && E.type_rows.bytes >= tr_bytes) {
+    P.type_rows = E.type_rows.as<uint64_t>();
+    P.n_types = g->n_labels;
+  }
   // vertices per block round of the vertex seeding: rows of Wp + 1 words in
   // at most 64 KB of LDS
   P.seed_vb = BLOCK;

@@ -127,6 +127,8 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
 
   LaneTables L;
   for (const LaneInfo &li : pk.lanes) L.add(g, li);
+  if (!export_only && type_rows_wanted(g) && seeds_by_vertex(g, L))
+    KWS_TRY(E.type_rows.ensure((size_t)g->n_labels * (size_t)Wp * 8, "type-row table"));
   // per level: lanes with d_max >= level, and the distance each level assigns
   std::vector<uint64_t> act((size_t)(D + 2) * Wp, 0);
   for (const LaneInfo &li : pk.lanes)
@@ -238,6 +240,7 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
   rec.alpha = o.alpha;
   rec.early = P.early != 0;
   rec.fused = fused;
+  rec.seed_table = P.type_rows != nullptr;
   return KWS_OK;
 }
 
@@ -261,6 +264,7 @@ kws_status finish_pass(kws_graph *g, PassRecord &rec, kws_result *out, FlatOut *
   const uint64_t *h_stats = (const uint64_t *)(io.h_arena.as<uint8_t>() + rec.al.extra);
   kws_batch_stats &bs = g->last;
   bs.fused_pull = rec.fused ? 1 : 0;
+  if (rec.seed_table) bs.seed_table = 1;
   if (rec.early) {
     const int32_t *h_stop = (const int32_t *)(io.h_arena.as<uint8_t>() + rec.al.early) + nq;
     for (int i = 0; i < nq; i++)
@@ -319,6 +323,7 @@ void default_options(kws_options *o) {
   o->count_te = 0;
   o->fused_pull = 0;
   o->early_stop = 0;
+  o->seed_table = 0;
 }
 
 namespace {

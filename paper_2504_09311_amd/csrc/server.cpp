@@ -337,7 +337,9 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
     return kws::fail(KWS_EINVAL, "tile_words must be 1, 2, 4, 8 or 16");
   int B = 0;
   while ((1 << B) <= o.max_dmax) B++;
-  const size_t per_word = (size_t)g->n * 8 * (4 + B);
+  // state arrays per word, and the type-row table's column of the word
+  const bool table = kws::type_rows_wanted(g);
+  const size_t per_word = (size_t)g->n * 8 * (4 + B) + (table ? (size_t)g->n_labels * 8 : 0);
   const size_t budget = o.mem_bytes ? (size_t)o.mem_bytes : g->mem_budget;
   int words = (int)std::min<size_t>(kws::MAX_WORDS, budget / std::max<size_t>(per_word, 1));
   if (o.max_words) words = std::min(words, o.max_words);
@@ -376,6 +378,7 @@ kws_status kws_server_create(kws_graph *g, const kws_server_opts *opts, kws_serv
   if (st == KWS_OK) st = s->eng.flags.ensure(2 * (size_t)g->n, "frontier flags");
   if (st == KWS_OK) st = s->live.ensure(2 * wp_alloc * 8, "live lanes");
   if (st == KWS_OK) st = s->stats.ensure(2 * kws::STAT_WORDS * 8, "step statistics");
+  if (st == KWS_OK && table) st = s->eng.type_rows.ensure((size_t)g->n_labels * wp_alloc * 8, "type-row table");
   if (st == KWS_OK && hipMemsetAsync(s->live.p, 0, 2 * wp_alloc * 8, s->stream) != hipSuccess)
     st = kws::fail(KWS_EDEVICE, "clearing server state failed");
   if (st == KWS_OK && hipMemsetAsync(s->stats.p, 0, 2 * kws::STAT_WORDS * 8, s->stream) != hipSuccess)

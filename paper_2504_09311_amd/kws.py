@@ -61,7 +61,7 @@ class Options(C.Structure):
     _fields_ = [("direction", C.c_int32), ("alpha", C.c_float), ("tile_words", C.c_int32),
                 ("block", C.c_int32), ("use_graph", C.c_int32), ("share_lanes", C.c_int32),
                 ("count_te", C.c_int32), ("seed_mode", C.c_int32), ("fused_pull", C.c_int32),
-                ("early_stop", C.c_int32)]
+                ("early_stop", C.c_int32), ("seed_table", C.c_int32)]
 
 
 class DsdDesc(C.Structure):
@@ -99,7 +99,8 @@ class BatchStats(C.Structure):
                 ("pulled", C.c_int32 * (MAX_LEVELS + 1)), ("frontier", C.c_int64 * (MAX_LEVELS + 1)),
                 ("frontier_edges", C.c_int64 * (MAX_LEVELS + 1)),
                 ("unfinished_edges", C.c_int64 * (MAX_LEVELS + 1)),
-                ("fused_pull", C.c_int32), ("early_stopped", C.c_int64), ("levels_skipped", C.c_int64)]
+                ("fused_pull", C.c_int32), ("early_stopped", C.c_int64), ("levels_skipped", C.c_int64),
+                ("seed_table", C.c_int32)]
 
     def as_dict(self):
         L = self.levels
@@ -109,7 +110,7 @@ class BatchStats(C.Structure):
                     frontier=list(self.frontier[:L + 1]), frontier_edges=list(self.frontier_edges[:L + 1]),
                     unfinished_edges=list(self.unfinished_edges[:L + 1]),
                     fused_pull=self.fused_pull, early_stopped=self.early_stopped,
-                    levels_skipped=self.levels_skipped)
+                    levels_skipped=self.levels_skipped, seed_table=self.seed_table)
 
 
 class ServerOpts(C.Structure):
@@ -400,11 +401,11 @@ class Graph:
     # ---- configuration and introspection
     def set_options(self, direction: int = 0, alpha: float = 0.0, tile_words: int = 0, use_graph: int = 0,
                     share_lanes: int = 0, count_te: int = 1, seed_mode: int = 0, fused_pull: int = 0,
-                    early_stop: int = -1):
+                    early_stop: int = -1, seed_table: int = 0):
         """Engine options (kws_set_options). count_te defaults to on and early_stop to off here, so
         that te is the full per-keyword scan count (a query that stops early counts fewer edges)."""
         o = Options(direction, alpha, tile_words, 0, use_graph, share_lanes, count_te, seed_mode, fused_pull,
-                    early_stop)
+                    early_stop, seed_table)
         _check(self._lib.kws_set_options(self.h, C.byref(o)))
 
     def autotune(self, queries, reps: int = 3, budget_ms: float = 0.0, cache_path: Optional[str] = None):

@@ -68,9 +68,11 @@ def test_tiny_random(K, block):
             assert_same(G.keyword_search(q.kw, q.d_max, q.k), want[i], f"tiny {seed} plain {i}")
         for direction in (0, 1, 2):
             fused = 1 if (seed + direction) % 2 else -1
+            table = 1 if (seed // 2 + direction) % 2 else -1
             G.set_options(direction=direction, tile_words=[1, 2, 4, 8, 16][seed % 5],
-                          share_lanes=1 if seed % 2 else -1, seed_mode=(seed + direction) % 3, fused_pull=fused)
-            assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction} fused {fused}")
+                          share_lanes=1 if seed % 2 else -1, seed_mode=(seed + direction) % 3, fused_pull=fused,
+                          seed_table=table)
+            assert_all_same(G.search_batch(qs), want, f"tiny {seed} batch dir {direction} fused {fused} table {table}")
         assert_all_same(G.search_batch_each(qs), want, f"tiny {seed} batch (per-query results)")
         G.close()
 
@@ -88,10 +90,11 @@ def test_tiny_batch_of_many_words(K):
     G = K.Graph.from_synth(g)
     for tw in (1, 4, 16):
         for share in (1, -1):
-            for sm in (1, 2):
-                say("many words", tw, share, sm)
-                G.set_options(tile_words=tw, share_lanes=share, seed_mode=sm, fused_pull=share)
-                assert_all_same(G.search_batch(qs), want, f"many tw {tw} share {share} seed {sm}")
+            for sm, table in ((1, 0), (2, -1), (2, 1)):
+                say("many words", tw, share, sm, table)
+                G.set_options(tile_words=tw, share_lanes=share, seed_mode=sm, fused_pull=share, seed_table=table)
+                assert_all_same(G.search_batch(qs), want, f"many tw {tw} share {share} seed {sm} table {table}")
+                assert G.last_batch_stats().seed_table == (1 if table == 1 else 0)
     G.close()
 
 
@@ -183,9 +186,9 @@ def test_rmat14_options_grid(K, rmat14):
         assert_all_same(G.search_batch(qs), want, f"rmat14 tw {tw} pull, unfused")
     G.set_options(share_lanes=-1)
     assert_all_same(G.search_batch(qs), want, "rmat14 no sharing")
-    for sm in (1, 2):
-        G.set_options(seed_mode=sm, tile_words=4)
-        assert_all_same(G.search_batch(qs), want, f"rmat14 seed mode {sm}")
+    for sm, table in ((1, 0), (2, -1), (2, 1)):
+        G.set_options(seed_mode=sm, tile_words=4, seed_table=table)
+        assert_all_same(G.search_batch(qs), want, f"rmat14 seed mode {sm} table {table}")
     G.set_options()
     for i in range(0, 96, 7):
         assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"rmat14 plain {i}")
@@ -199,9 +202,13 @@ def test_rmat14_hierarchy(K):
     G = K.Graph.from_synth(g)
     for direction in (0, 1, 2):
         for sm in (0, 1, 2):
-            say("rmat14 hier", direction, sm)
-            G.set_options(direction=direction, seed_mode=sm, fused_pull=-1 if sm == 1 else 1)
-            assert_all_same(G.search_batch(qs), want, f"hier dir {direction} seed {sm}")
+            # the type-row table on for vertex seeding (every type's row walks its ancestors)
+            table = 1 if (sm + direction) % 2 else -1
+            say("rmat14 hier", direction, sm, table)
+            G.set_options(direction=direction, seed_mode=sm, fused_pull=-1 if sm == 1 else 1, seed_table=table)
+            assert_all_same(G.search_batch(qs), want, f"hier dir {direction} seed {sm} table {table}")
+            if sm == 2:
+                assert G.last_batch_stats().seed_table == (1 if table == 1 else 0)
     G.set_options()
     for i in range(0, 64, 9):
         assert_same(G.keyword_search(qs[i].kw, qs[i].d_max, qs[i].k), want[i], f"hier plain {i}")

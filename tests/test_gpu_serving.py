@@ -73,12 +73,32 @@ def test_served_tiny_graphs(K):
         o = oracle.Oracle(g)
         want = [o.search(q.kw, q.d_max, q.k) for q in qs]
         G = K.Graph.from_synth(g)
+        # a server takes the graph's seeding options when it is created
+        table = 1 if seed % 2 else -1
+        G.set_options(seed_mode=2 if seed % 3 else 0, seed_table=table)
         S = K.Server(G, max_words=3, tile_words=1)
         ts = [S.submit(q.kw, q.d_max, q.k) for q in qs]
         got = [S.wait(t, 30.0) for t in ts]
-        assert_all_same(got, want, f"served tiny {seed}")
+        assert_all_same(got, want, f"served tiny {seed} table {table}")
         S.close()
         G.close()
+
+
+def test_served_type_hierarchy(K):
+    # vertex seeding through the type-row table and by walking each label
+    g, leaves = workloads.rmat_hier(12, cfg=4)
+    qs = workloads.rmat_hier_queries(g.type_parent, leaves, 48, cfg=4)
+    want = oracle_results(oracle.Oracle(g), qs)
+    G = K.Graph.from_synth(g)
+    for table in (1, -1):
+        say("served hierarchy, table", table)
+        G.set_options(seed_mode=2, seed_table=table)
+        S = K.Server(G, max_words=4, max_dmax=4, tile_words=2)
+        ts = [S.submit(q.kw, q.d_max, q.k) for q in qs]
+        got = [S.wait(t, 60.0) for t in ts]
+        assert_all_same(got, want, f"served hierarchy table {table}")
+        S.close()
+    G.close()
 
 
 def test_server_cancel_busy_and_shutdown(K, rmat14):
