@@ -285,6 +285,81 @@ __global__ __launch_bounds__(BLOCK) void k_seed_level0(const Pass *__restrict__ 
   }
 }
 
+// ---- k_seed_level0 from the type-row table, tiles of T >= 2 words: no LDS
+// rows. A group of T / 2 threads owns one vertex, each thread two words of
+// every tile (16-byte table loads, 16-byte stores of vis and the first
+// frontier), so a wavefront writes the whole tile rows of 128 / T vertices
+// in one contiguous run. The frontier flag, the level-0 statistics and the
+// live lanes are reduced across the group and the wavefront by ballot and
+// shuffles.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+template <int T>
+__global__ __launch_bounds__(BLOCK) void k_seed_level0_tab(const Pass *__restrict__ Pp, const Step *__restrict__ Sp) {
+  static_assert(T >= 2, "two words per thread");
+  constexpr int G = T / 2, VPW = 64 / G;
+  const Pass &P = *Pp;
+  const Step &S = *Sp;
+  extern __shared__ uint64_t s_live[];   // [Wp]
+  const int tid = threadIdx.x, lane = tid & 63, t = lane % G;
+  const uint64_t gmask = group_bits(lane, G);
+  for (int j = tid; j < P.Wp; j += BLOCK) s_live[j] = 0;
+  __syncthreads();
+  uint64_t nf_acc = 0, mf_acc = 0, mu_acc = 0;
+  const int64_t wave = ((int64_t)blockIdx.x * BLOCK + tid) / 64, nwaves = (int64_t)gridDim.x * (BLOCK / 64);
+  for (int64_t v0 = wave * VPW; v0 < P.n; v0 += nwaves * VPW) {
+    const int64_t v = v0 + lane / G;
+    const bool valid = v < P.n;
+    int32_t a = 0, b = 0;
+    if (valid) { a = P.lab_ptr[v]; b = P.lab_ptr[v + 1]; }
+    bool anyf = false, anyneed = false;
+    for (int tile = 0; tile < P.tiles; tile++) {
+      const int j = tile * T + 2 * t;
+      u64x2 m = {0ull, 0ull};
+      for (int32_t l = a; l < b; l++) m |= *(const u64x2 *)(P.type_rows + (size_t)P.lab[l] * P.Wp + j);
+      if (valid) {
+        const size_t idx = ((size_t)tile * P.n + v) * T + 2 * t;
+        __builtin_nontemporal_store(m, (u64x2 *)(P.vis + idx));
+        if (S.write_next) __builtin_nontemporal_store(m, (u64x2 *)(S.fr_next + idx));
+        anyf |= (m.x | m.y) != 0;
+        anyneed |= ((S.act_nn[j] & ~m.x) | (S.act_nn[j + 1] & ~m.y)) != 0;
+      }
+      if (S.write_next) {
+        uint64_t lx = m.x, ly = m.y;
+        for (int off = G; off < 64; off <<= 1) {
+          lx |= __shfl_xor(lx, off);
+          ly |= __shfl_xor(ly, off);
+        }
+        if (lane < G) {
+          if (lx) atomicOr((unsigned long long *)&s_live[j], (unsigned long long)lx);
+          if (ly) atomicOr((unsigned long long *)&s_live[j + 1], (unsigned long long)ly);
+        }
+      }
+    }
+    const bool fflag = (__ballot(anyf) & gmask) != 0, nflag = (__ballot(anyneed) & gmask) != 0;
+    if (valid && t == 0) {
+      if (S.build_list) S.flags_next[v] = fflag ? 1 : 0;
+      if (fflag) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
+      if (nflag && S.write_next) mu_acc += (uint64_t)(P.fwd_ptr[v + 1] - P.fwd_ptr[v]);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nf_acc += __shfl_xor(nf_acc, off);
+    mf_acc += __shfl_xor(mf_acc, off);
+    mu_acc += __shfl_xor(mu_acc, off);
+  }
+  if (lane == 0) {
+    uint64_t *st = stat_stripe(S.st_out, blockIdx.x);
+    if (nf_acc) atomicAdd((unsigned long long *)&st[0], (unsigned long long)((nf_acc << 32) | mf_acc));
+    if (mu_acc) atomicAdd((unsigned long long *)&st[1], (unsigned long long)mu_acc);
+  }
+  if (S.write_next) {
+    __syncthreads();
+    for (int j = tid; j < P.Wp; j += BLOCK)
+      if (s_live[j]) atomicOr((unsigned long long *)&S.live_out[j], s_live[j]);
+  }
+}
+
 // ---- finalize one step: new = nxt & ~vis & act_new; vis |= new; distance
 // planes; next frontier buffer; nxt cleared; a frontier flag per vertex;
 // the statistics that pick the direction of the next level (frontier size,
@@ -1714,6 +1789,20 @@ kws_status launch_seed_level0(const Pass &P, const Step &S, hipStream_t s, Profi
   const int64_t zwords = launch_size(P, std::max(P.zero0_words, std::max(P.zero1_words, P.zero2_words)));
   if (zwords > 0) k_zero_pass<<<clamp_grid((zwords + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(P.dev);
   launch_type_rows(P, s);
+  if (P.type_rows && P.T >= 2) {
+    // T / 2 threads per vertex: 128 / T vertices per wavefront
+    const int64_t per_block = (int64_t)(BLOCK / 64) * (128 / P.T);
+    const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(((int64_t)P.n + per_block - 1) / per_block, 1), 8192));
+    const size_t lds_t = sizeof(uint64_t) * (size_t)P.Wp;
+    switch (P.T) {
+      case 2: k_seed_level0_tab<2><<<grid, BLOCK, lds_t, s>>>(P.dev, S.dev); break;
+      case 4: k_seed_level0_tab<4><<<grid, BLOCK, lds_t, s>>>(P.dev, S.dev); break;
+      case 8: k_seed_level0_tab<8><<<grid, BLOCK, lds_t, s>>>(P.dev, S.dev); break;
+      case 16: k_seed_level0_tab<16><<<grid, BLOCK, lds_t, s>>>(P.dev, S.dev); break;
+      default: return fail(KWS_EINVAL, "tile width %d not supported", P.T);
+    }
+    return launch_check("seed");
+  }
   const int64_t vblocks = ((int64_t)P.n + P.seed_vb - 1) / P.seed_vb;
   const int grid = clamp_grid(std::min<int64_t>(std::max<int64_t>(vblocks, 1), 4096));
   const size_t lds = sizeof(uint64_t) * ((size_t)P.seed_vb * (size_t)(P.Wp + 1) + (size_t)P.Wp) +

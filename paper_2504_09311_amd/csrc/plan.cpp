@@ -302,7 +302,7 @@ bool seeds_by_vertex(const kws_graph *g, const LaneTables &L) {
 // replaces (one per vertex label), and it stays small against a state array
 bool type_rows_wanted(const kws_graph *g) {
   const int o = g->opt.seed_table;
-  return o > 0 || (o == 0 && 2 * (int64_t)g->n_labels <= std::min<int64_t>(g->n, g->h_lab_total));
+  return o > 0 || (o == 0 && 8 * (int64_t)g->n_labels <= std::min<int64_t>(g->n, g->h_lab_total));
 }
 
 void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const LaneTables &L,
