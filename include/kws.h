@@ -221,9 +221,10 @@ typedef struct {
                             of n_labels rows of words: row t holds the lanes whose keyword is t or an
                             ancestor of t, built by one walk per type, so a vertex ORs the rows of its
                             labels instead of walking and hashing each label's ancestors. 0 (default):
-                            when the label count is at most an eighth of both the vertex count and
-                            the (vertex, label) pair count; 1: always; -1: never. The table takes
-                            8 * n_labels bytes per word of the batch */
+                            when the labels have a type hierarchy and the label count is at most an
+                            eighth of both the vertex count and the (vertex, label) pair count;
+                            1: always; -1: never. The table takes 8 * n_labels bytes per word of
+                            the batch */
 } kws_options;
 kws_status kws_set_options(kws_graph *g, const kws_options *opt);
 kws_status kws_get_options(kws_graph *g, kws_options *opt);

@@ -298,11 +298,14 @@ bool seeds_by_vertex(const kws_graph *g, const LaneTables &L) {
   return L.n() > 0 && (mode == 2 || (mode == 0 && L.seed_off.back() > (int64_t)g->n + lab_total * (1 + g->type_depth)));
 }
 
-// the table pays when its walks (one per type) are few against the walks it
-// replaces (one per vertex label), and it stays small against a state array
+// the table pays when the walks it replaces (one per vertex label) climb a
+// type hierarchy, its own walks (one per type) are few against them, and
+// it stays small against a state array; a flat label is one hash probe,
+// cheaper than building the table
 bool type_rows_wanted(const kws_graph *g) {
   const int o = g->opt.seed_table;
-  return o > 0 || (o == 0 && 8 * (int64_t)g->n_labels <= std::min<int64_t>(g->n, g->h_lab_total));
+  return o > 0 || (o == 0 && g->type_depth > 0 &&
+                   8 * (int64_t)g->n_labels <= std::min<int64_t>(g->n, g->h_lab_total));
 }
 
 void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const LaneTables &L,
