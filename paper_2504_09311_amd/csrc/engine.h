@@ -54,6 +54,7 @@ struct QueryTables {
   std::vector<uint64_t> mask;
   std::vector<int32_t> word, dmax, nk, kcap, hoff, coff, ccap, roff, kdoff, eoff, ecap, boff;
   std::vector<int32_t> seed_b, seed_e, wq_ptr, wq;
+  std::vector<QWord> qw;
   std::vector<uint8_t> bits;
   int64_t nhist = 0, ncand = 0, nslots = 0, nkd = 0, nedge = 0;
   int32_t chunks = 1, CH = 64;
@@ -112,7 +113,7 @@ struct AsyncBatch {
 // Offsets of the query tables inside the plan buffer.
 struct QueryOffsets {
   size_t mask, word, dmax, nk, kcap, hoff, coff, ccap, roff, kdoff, eoff, ecap, boff, seed_b, seed_e, wq_ptr,
-      wq, bits;
+      wq, qw, bits;
 };
 QueryOffsets add_query_tables(PlanWriter &pw, const QueryTables &Q);
 

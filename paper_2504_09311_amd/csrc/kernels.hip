@@ -920,13 +920,14 @@ __global__ __launch_bounds__(BLOCK) void k_fin_stats(const Pass *__restrict__ Pp
 // optionally the scanned-edge count te (in-degree of every vertex each lane
 // expanded). A thread owns one vertex and holds the T words of one tile
 // (vis and distance planes) in registers; a wavefront walks the words and
-// their queries in lockstep. With L, the per-query table (mask, histogram
-// offset, d_max, query id, in word order), the chunk's histogram and the te
-// sums live in LDS, so the query loop issues no global load and the
-// histogram adds are LDS atomics; without L (batches too large for LDS)
-// the same loop reads the tables from global memory and adds there. TE
-// (count_te) is a template argument so that the query loop carries no te
-// work when it is off; the loop bounds are wavefront-uniform scalars.
+// their queries in lockstep, so the word -> query offsets and the query
+// table (mask, histogram offset, query id, d_max, in word order) are read
+// through the constant address space: scalar loads into SGPRs, operands of
+// the vector ops without copies. With L the chunk's histogram (and the te
+// sums) live in LDS and the histogram adds are LDS atomics; without L
+// (batches too large for LDS) they go to global memory. TE (count_te) is a
+// template argument so that the query loop carries no te work when it is
+// off.
 // With FIN the kernel also does the finalize of the last level (step F, in
 // a batched pass, where nothing follows that level): it reads nxt beside
 // vis and the planes, merges the arrivals in registers, writes back only
@@ -935,26 +936,16 @@ template <int T, bool L, bool TE, bool FIN, int PB>
 __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, const Step *__restrict__ Fp) {
   const Pass &P = *Pp;
   extern __shared__ uint64_t s_dyn[];
-  uint64_t *s_te = s_dyn;                                   // [nq] (count_te)
-  uint64_t *s_qm = s_dyn + P.nq;                            // [nq] masks in word order
-  int32_t *s_qh = (int32_t *)(s_qm + P.nq);                 // [nq] histogram offsets
-  int32_t *s_qd = s_qh + P.nq;                              // [nq] d_max
-  int32_t *s_qx = s_qd + P.nq;                              // [nq] query ids
-  int32_t *s_wqp = s_qx + P.nq;                            // [Wp + 1] word -> first query
-  int32_t *s_hist = s_wqp + P.Wp + 1;                       // [nhist]
+  uint64_t *s_te = s_dyn;                                   // [nq] in word order (count_te)
+  int32_t *s_hist = (int32_t *)(s_dyn + (TE ? P.nq : 0));   // [nhist]
+  typedef const __attribute__((address_space(4))) QWord *QWordC;
+  typedef const __attribute__((address_space(4))) int32_t *I32C;
+  const QWordC qw = (QWordC)P.qw;
+  const I32C wqp = (I32C)P.word_q_ptr;
   const int tid = threadIdx.x, lane = tid & 63;
   const int split = (P.CH + BLOCK - 1) / BLOCK;
-  if (L) {
-    for (int i = tid; i <= P.Wp; i += BLOCK) s_wqp[i] = P.word_q_ptr[i];
-    for (int i = tid; i < P.nq; i += BLOCK) {
-      const int q = P.word_q[i];
-      s_te[i] = 0;
-      s_qm[i] = P.q_mask[q];
-      s_qh[i] = P.q_hoff[q];
-      s_qd[i] = P.q_dmax[q];
-      s_qx[i] = q;
-    }
-  }
+  if (L && TE)
+    for (int i = tid; i < P.nq; i += BLOCK) s_te[i] = 0;
   uint64_t nf_acc = 0, mf_acc = 0;        // FIN: frontier of the last level
   for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
     const int c = (int)(bid / split), part = (int)(bid % split);
@@ -965,7 +956,6 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
     const int64_t v = (int64_t)c * P.CH + (int64_t)part * BLOCK + tid;
     const bool valid = v < cend;
     const uint64_t indeg = (TE && valid) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
-    const int32_t *wqp = L ? s_wqp : P.word_q_ptr;
     // words held in registers at a time: a whole 16-word row when at most
     // two planes are used (the row's lines are then read once; in halves,
     // they are mostly evicted before the second half is read)
@@ -1065,21 +1055,30 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
 #pragma unroll
         for (int w = 0; w < H; w++) {
           const int j = tile * T + h0 + w;
+          // uniform by construction; readfirstlane lets the compiler see it
+          // (the query index then stays scalar and the table loads are
+          // scalar loads in every variant)
           const int qb = __builtin_amdgcn_readfirstlane(wqp[j]), qe = __builtin_amdgcn_readfirstlane(wqp[j + 1]);
           if (qb == qe || __ballot(vis[w] != 0) == 0) continue;
-          // a plain loop over the word's queries, the next mask loaded ahead;
-          // invalid lanes miss every lane, so they are never roots. Planes
-          // past P.B hold zero in registers and every d_max is below 2^P.B,
-          // so no plane needs a bound check here.
+          // a plain loop over the word's queries; invalid lanes miss every
+          // lane, so they are never roots. Planes past P.B hold zero in
+          // registers and every d_max is below 2^P.B, so no plane needs a
+          // bound check here.
           const uint64_t miss = valid ? ~vis[w] : ~0ull;
-          uint64_t m_next = L ? s_qm[qb] : P.q_mask[P.word_q[qb]];
+          // the next query's mask and histogram offset, loaded a query ahead
+          uint64_t m_next = qw[qb].mask;
+          int32_t h_next = qw[qb].hoff;
           for (int qi = qb; qi < qe; qi++) {
             const uint64_t m = m_next;
-            if (qi + 1 < qe) m_next = L ? s_qm[qi + 1] : P.q_mask[P.word_q[qi + 1]];
+            const int32_t hoff = h_next;
+            if (qi + 1 < qe) {
+              m_next = qw[qi + 1].mask;
+              h_next = qw[qi + 1].hoff;
+            }
             const bool root = (m & miss) == 0;
             if (TE) {
-              const int q = L ? s_qx[qi] : P.word_q[qi];
-              const int dq = L ? s_qd[qi] : P.q_dmax[q];
+              const int q = qw[qi].q;
+              const int dq = qw[qi].dmax;
               const uint64_t x = vis[w] & m;
               uint64_t eq = x;
 #pragma unroll
@@ -1093,13 +1092,13 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
                 }
               }
             }
-            if (__ballot(root) == 0) continue;      // no root of this query in the wavefront
+            if (__builtin_amdgcn_ballot_w64(root) == 0) continue;   // no root of this query in the wavefront
             int sc = 0;
 #pragma unroll
             for (int b = 0; b < PB; b++) sc += __popcll(pl[b][w] & m) << b;
             if (root) {
-              if (L) atomicAdd(&s_hist[s_qh[qi] + sc], 1);
-              else atomicAdd(&P.hist[(size_t)c * P.nhist + P.q_hoff[P.word_q[qi]] + sc], 1);
+              if (L) atomicAdd(&s_hist[hoff + sc], 1);
+              else atomicAdd(&P.hist[(size_t)c * P.nhist + hoff + sc], 1);
             }
           }
         }
@@ -1115,7 +1114,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
   if (L && TE) {
     __syncthreads();
     for (int i = tid; i < P.nq; i += BLOCK)
-      if (s_te[i]) atomicAdd((unsigned long long *)&P.te[s_qx[i]], (unsigned long long)s_te[i]);
+      if (s_te[i]) atomicAdd((unsigned long long *)&P.te[P.qw[i].q], (unsigned long long)s_te[i]);
   }
   if (FIN) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -1552,8 +1551,8 @@ inline int64_t launch_size(const Pass &P, int64_t x) {
 }
 
 inline size_t score_lds(const Pass &P) {
-  return P.hist_lds ? (size_t)launch_size(P, (int64_t)((size_t)P.nq * (8 + 8 + 4 + 4 + 4) +
-                                                      sizeof(int32_t) * ((size_t)P.Wp + 1 + (size_t)P.nhist)))
+  return P.hist_lds ? (size_t)launch_size(P, (int64_t)((P.count_te ? (size_t)P.nq * 8 : 0) +
+                                                      sizeof(int32_t) * (size_t)P.nhist))
                     : 0;
 }
 

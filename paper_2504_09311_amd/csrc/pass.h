@@ -19,6 +19,17 @@
 
 namespace kws {
 
+// What the score step reads of one query, in word order (queries of word j
+// at [word_q_ptr[j], word_q_ptr[j + 1])): uniform across a wavefront, so
+// its fields come in through scalar loads.
+struct QWord {
+  uint64_t mask;       // the query's lanes in its word
+  int32_t hoff;        // its histogram's offset in a chunk's histogram
+  int32_t q;           // query index in the pass
+  int32_t dmax;
+  int32_t pad;
+};
+
 struct Pass {
   const Pass *dev;                   // where this descriptor lives in device memory (kernels read it there)
   int32_t graph_mode;                // launch grids depend on the pass shape only (captured graphs replay)
@@ -55,6 +66,7 @@ struct Pass {
   const int32_t *lane_word, *lane_bit;
   // queries to finish (score, rank, answer)
   const int32_t *word_q_ptr, *word_q;
+  const QWord *qw;                   // [nq] in word order
   const uint64_t *q_mask;
   const int32_t *q_word, *q_dmax, *q_nk, *q_kcap, *q_hoff, *q_coff, *q_ccap, *q_roff, *q_kdoff,
       *q_eoff, *q_ecap, *q_boff;

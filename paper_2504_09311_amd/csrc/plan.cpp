@@ -177,6 +177,11 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
   for (int j = 0; j < Wp; j++) wq_ptr[j + 1] += wq_ptr[j];
   std::vector<int32_t> fill(wq_ptr.begin(), wq_ptr.end() - 1);
   for (int i = 0; i < nq; i++) wq[fill[word[i]]++] = i;
+  qw.resize(nq);
+  for (int i = 0; i < nq; i++) {
+    const int q = wq[i];
+    qw[i] = QWord{mask[q], hoff[q], q, dmax[q], 0};
+  }
   // chunks of about 1024 vertices (the select step scans whole chunks for
   // the few that hold a selected root), as long as the histograms (one
   // int per chunk and histogram bin) stay within 512 MB
@@ -184,9 +189,9 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
   chunks = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n + 1023) / 1024, hist_cap));
   CH = (int)align_up((size_t)((n + chunks - 1) / chunks), 64);
   chunks = (n + CH - 1) / CH;
-  // the score step keeps the query table (28 bytes per query), the word ->
-  // query offsets and one chunk's histogram in at most 64 KB of LDS
-  hist_lds = (size_t)nq * 28 + ((size_t)Wp + 1 + (size_t)nhist) * 4 <= 65536;
+  // the score step keeps one chunk's histogram (and, counting te, a sum
+  // per query) in at most 64 KB of LDS
+  hist_lds = (size_t)nq * 8 + (size_t)nhist * 4 <= 65536;
   te_lds = hist_lds;
   if ((size_t)chunks * (size_t)nhist > (size_t)INT32_MAX) return fail(KWS_EOVERFLOW, "histogram too large");
   return KWS_OK;
@@ -247,6 +252,7 @@ QueryOffsets add_query_tables(PlanWriter &pw, const QueryTables &Q) {
   o.seed_e = pw.add(Q.seed_e.data(), Q.seed_e.size() * 4);
   o.wq_ptr = pw.add(Q.wq_ptr.data(), Q.wq_ptr.size() * 4);
   o.wq = pw.add(Q.wq.data(), Q.wq.size() * 4);
+  o.qw = pw.add(Q.qw.data(), Q.qw.size() * sizeof(QWord));
   o.bits = pw.add(Q.bits.data(), Q.bits.size());
   return o;
 }
@@ -385,6 +391,7 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.qk_seed_e = (const int32_t *)(dp + qo.seed_e);
   P.word_q_ptr = (const int32_t *)(dp + qo.wq_ptr);
   P.word_q = (const int32_t *)(dp + qo.wq);
+  P.qw = (const QWord *)(dp + qo.qw);
   P.bits = dp + qo.bits;
   uint8_t *ar = E.io().arena.as<uint8_t>();
   uint8_t *zr = E.io().zero_region.as<uint8_t>();
