@@ -956,10 +956,10 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
     const int64_t v = (int64_t)c * P.CH + (int64_t)part * BLOCK + tid;
     const bool valid = v < cend;
     const uint64_t indeg = (TE && valid) ? (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]) : 0ull;
-    // words held in registers at a time: a whole 16-word row when at most
-    // two planes are used (the row's lines are then read once; in halves,
-    // they are mostly evicted before the second half is read)
-    constexpr int H = (T == 16 && PB == 2) ? 16 : (T < 8 ? T : 8);
+    // words held in registers at a time: at most 8 (a 16-word row in two
+    // halves; whole rows need about 120 VGPRs, four waves per SIMD, and the
+    // query loop wants the occupancy more than the row wants one read)
+    constexpr int H = (T < 8 ? T : 8);
     bool anyf = false;
     for (int tile = 0; tile < P.tiles; tile++) {
 #pragma unroll 1
