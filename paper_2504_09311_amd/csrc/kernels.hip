@@ -697,17 +697,26 @@ __global__ __launch_bounds__(BLOCK) void k_pull(const Pass *__restrict__ Pp, con
 // planes and flag bytes.
 
 // One vertex-word of a finalize at a level >= 1: writes vis, the planes
-// and the next frontier; returns the new vis word.
+// and the next frontier; returns the new vis word. The active lanes of
+// `gmask` hold the words of one vertex-tile row: where any of them gains
+// lanes, all of them write vis (and the planes that are OR-ed at this
+// level) back, so each row is one whole-line write instead of a partial
+// line that the memory must read back to merge.
 __device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_t idx, int j, uint64_t old,
-                                             uint64_t fnew) {
+                                             uint64_t fnew, uint64_t gmask) {
   const int nl = S.newlvl[j];
   const bool first_store = !S.clear_planes;
   const int rmw = first_store && (nl & (nl - 1)) == 0 ? 0 : nl;
   const uint64_t nv = old | fnew;
-  if (fnew) P.vis[idx] = nv;
+  const bool rowf = (__ballot(fnew != 0) & gmask) != 0;
+  if (rowf) P.vis[idx] = nv;
   for (int b = 0; b < P.B; b++) {
-    if (first_store && nl == (1 << b)) P.planes[b * P.pstride + idx] = fnew;
-    else if (fnew && ((rmw >> b) & 1)) P.planes[b * P.pstride + idx] |= fnew;
+    if (first_store && nl == (1 << b)) {
+      P.planes[b * P.pstride + idx] = fnew;
+    } else if (rowf && ((rmw >> b) & 1)) {
+      uint64_t *pp = &P.planes[b * P.pstride + idx];
+      *pp = *pp | fnew;
+    }
   }
   if (S.write_next) __builtin_nontemporal_store(fnew, &S.fr_next[idx]);
   return nv;
@@ -763,7 +772,7 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
     bool anyf = false, anyneed = false;
     if (eo == 0) {
       const uint64_t fnew = acc & need & an;
-      const uint64_t nv = fin_word(P, SP, idx, j, old, fnew);
+      const uint64_t nv = fin_word(P, SP, idx, j, old, fnew, gmask);
       if (SP.write_next) live_acc |= fnew;
       anyf = fnew != 0;
       anyneed = (ann & ~nv) != 0;
@@ -875,7 +884,7 @@ __global__ __launch_bounds__(BLOCK) void k_fin_list(const Pass *__restrict__ Pp,
     const size_t idx = (size_t)tile * P.n * T + (size_t)v * T + w;
     const uint64_t old = P.vis[idx], nx = P.nxt[idx];
     const uint64_t fnew = nx & ~old & S.act_new[j];
-    const uint64_t nv = fin_word(P, S, idx, j, old, fnew);
+    const uint64_t nv = fin_word(P, S, idx, j, old, fnew, gmask);
     if (nx) P.nxt[idx] = 0ull;
     if (fnew && S.write_next) atomicOr((unsigned long long *)&s_live[j], fnew);
     const bool fflag = (__ballot(fnew != 0) & gmask) != 0;
