@@ -1075,15 +1075,15 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
           // bound check here.
           const uint64_t miss = valid ? ~vis[w] : ~0ull;
           // the next query's mask and histogram offset, loaded a query ahead
+          // (the table ends with a zero entry, so no bound check)
           uint64_t m_next = qw[qb].mask;
           int32_t h_next = qw[qb].hoff;
+#pragma unroll 2
           for (int qi = qb; qi < qe; qi++) {
             const uint64_t m = m_next;
             const int32_t hoff = h_next;
-            if (qi + 1 < qe) {
-              m_next = qw[qi + 1].mask;
-              h_next = qw[qi + 1].hoff;
-            }
+            m_next = qw[qi + 1].mask;
+            h_next = qw[qi + 1].hoff;
             const bool root = (m & miss) == 0;
             if (TE) {
               const int q = qw[qi].q;
@@ -1101,11 +1101,10 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
                 }
               }
             }
-            if (__builtin_amdgcn_ballot_w64(root) == 0) continue;   // no root of this query in the wavefront
-            int sc = 0;
+            if (root) {                             // skipped as a whole when no lane has a root
+              int sc = 0;
 #pragma unroll
-            for (int b = 0; b < PB; b++) sc += __popcll(pl[b][w] & m) << b;
-            if (root) {
+              for (int b = 0; b < PB; b++) sc += __popcll(pl[b][w] & m) << b;
               if (L) atomicAdd(&s_hist[hoff + sc], 1);
               else atomicAdd(&P.hist[(size_t)c * P.nhist + hoff + sc], 1);
             }

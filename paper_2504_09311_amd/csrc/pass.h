@@ -66,7 +66,7 @@ struct Pass {
   const int32_t *lane_word, *lane_bit;
   // queries to finish (score, rank, answer)
   const int32_t *word_q_ptr, *word_q;
-  const QWord *qw;                   // [nq] in word order
+  const QWord *qw;                   // [nq + 1] in word order, the last entry zero
   const uint64_t *q_mask;
   const int32_t *q_word, *q_dmax, *q_nk, *q_kcap, *q_hoff, *q_coff, *q_ccap, *q_roff, *q_kdoff,
       *q_eoff, *q_ecap, *q_boff;

@@ -177,7 +177,9 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
   for (int j = 0; j < Wp; j++) wq_ptr[j + 1] += wq_ptr[j];
   std::vector<int32_t> fill(wq_ptr.begin(), wq_ptr.end() - 1);
   for (int i = 0; i < nq; i++) wq[fill[word[i]]++] = i;
-  qw.resize(nq);
+  // one entry more than queries (all zero), so that the score loop can load
+  // the entry after a word's last query without a bound check
+  qw.assign(nq + 1, QWord{0, 0, 0, 0, 0});
   for (int i = 0; i < nq; i++) {
     const int q = wq[i];
     qw[i] = QWord{mask[q], hoff[q], q, dmax[q], 0};
