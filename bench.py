@@ -261,7 +261,8 @@ def serve_bench(G, K, g, qs, args):
                 poisson=runs)
 
 
-PEEL_METRIC = "densest-subgraph parallel peeling (eps=0.1): edges per second over a full run; rounds; time"
+PEEL_METRIC = ("densest-subgraph parallel peeling (eps=0.1): input edges per second of a full run "
+               "(input size over run time, not incidences read); rounds; time")
 
 
 def peel_bytes(metric: str, n: int, sizes, summary) -> dict:

@@ -582,6 +582,49 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass *__restrict__ Pp, con
   }
 }
 
+// ---- the gather of one row by its group of S = T*E threads: thread (eo, w)
+// ORs word w of the frontier rows of edges eo, eo + E, ... of [eb, ee),
+// rounds of U edges per thread, and stops once the group has every lane
+// the vertex still misses. The column indices of a round are loaded
+// coalesced, lane i of the group taking edge i (ceil(U / T) loads of S
+// indices), and each thread takes its U indices from those lanes by
+// shuffle; the next round's loads are in flight while this round gathers.
+// Returns the thread's partial OR (not yet combined over eo).
+template <int T, int S, int U>
+__device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ fr, const int32_t *__restrict__ col,
+                                               int32_t eb, int32_t ee, uint64_t need, int gl, int w, int eo,
+                                               uint64_t gmask) {
+  constexpr int E = S / T, NL = (U + T - 1) / T;
+  uint64_t acc = 0;
+  int32_t c[NL], cn[NL], x[U];
+#pragma unroll
+  for (int k = 0; k < NL; k++) {
+    const int32_t e = eb + k * S + gl;
+    c[k] = e < ee ? col[e] : -1;
+  }
+  for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = __shfl(c[u / T], (u % T) * E + eo, S);
+#pragma unroll
+    for (int k = 0; k < NL; k++) {
+      const int32_t e = e0 + E * U + k * S + gl;
+      cn[k] = e < ee ? col[e] : -1;
+    }
+    // a thread whose word has found every missing lane stops gathering
+    const bool want = (acc & need) != need;
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
+    uint64_t r = acc;
+#pragma unroll
+    for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
+    if ((__ballot((r & need) != need) & gmask) == 0) break;
+#pragma unroll
+    for (int k = 0; k < NL; k++) c[k] = cn[k];
+  }
+  return acc;
+}
+
 // ---- pull: a group of S = T*E threads owns one row (or one hub chunk);
 // thread (e, w) ORs word w of the frontier mask of every E-th out-neighbour.
 // Early exit once the group has found every lane the vertex still misses.
@@ -590,7 +633,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass *__restrict__ Pp, con
 template <int T, int S, bool SEG>
 __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                           int tile, int bb, int bpt) {
-  constexpr int E = S / T, GPB = BLOCK / S, U = 8;
+  constexpr int GPB = BLOCK / S, U = 8;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -609,34 +652,7 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
     }
     const uint64_t need = actw & ~vis[(size_t)v * T + w];
     if ((__ballot(need != 0) & gmask) == 0) continue;
-    uint64_t acc = 0;
-    // the column indices of the next round are loaded while this round's
-    // frontier words are gathered: one memory round trip per round
-    int32_t x[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int32_t e = eb + u * E + eo;
-      x[u] = e < ee ? col[e] : -1;
-    }
-    for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
-      int32_t xn[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int32_t e = e0 + E * U + u * E + eo;
-        xn[u] = e < ee ? col[e] : -1;
-      }
-      // a thread whose word has found every missing lane stops gathering
-      const bool want = (acc & need) != need;
-#pragma unroll
-      for (int u = 0; u < U; u++)
-        if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
-      uint64_t r = acc;
-#pragma unroll
-      for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
-      if ((__ballot((r & need) != need) & gmask) == 0) break;
-#pragma unroll
-      for (int u = 0; u < U; u++) x[u] = xn[u];
-    }
+    uint64_t acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask);
 #pragma unroll
     for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
     acc &= need;
@@ -725,7 +741,7 @@ __device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_
 template <int T, int S>
 __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                               int tile, int bb, int bpt, uint64_t &live_acc) {
-  constexpr int E = S / T, GPB = BLOCK / S, U = 8;
+  constexpr int GPB = BLOCK / S, U = 8;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -742,30 +758,7 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
     const uint64_t need = actw & ~old;
     uint64_t acc = 0;
     if ((__ballot(need != 0) & gmask) != 0) {
-      int32_t x[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int32_t e = eb + u * E + eo;
-        x[u] = e < ee ? col[e] : -1;
-      }
-      for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
-        int32_t xn[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          const int32_t e = e0 + E * U + u * E + eo;
-          xn[u] = e < ee ? col[e] : -1;
-        }
-        const bool want = (acc & need) != need;
-#pragma unroll
-        for (int u = 0; u < U; u++)
-          if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
-        uint64_t r = acc;
-#pragma unroll
-        for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
-        if ((__ballot((r & need) != need) & gmask) == 0) break;
-#pragma unroll
-        for (int u = 0; u < U; u++) x[u] = xn[u];
-      }
+      acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask);
 #pragma unroll
       for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
     }
