@@ -584,8 +584,9 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass *__restrict__ Pp, con
 
 // ---- the gather of one row by its group of S = T*E threads: thread (eo, w)
 // ORs word w of the frontier rows of edges eo, eo + E, ... of [eb, ee),
-// rounds of U edges per thread, and stops once the group has every lane
-// the vertex still misses. The column indices of a round are loaded
+// rounds of U edges per thread (the pulls use 4: the early-exit test comes
+// after fewer gathers and the round holds fewer registers), and stops once
+// the group has every lane the vertex still misses. The column indices of a round are loaded
 // coalesced, lane i of the group taking edge i (ceil(U / T) loads of S
 // indices), and each thread takes its U indices from those lanes by
 // shuffle; the next round's loads are in flight while this round gathers.
@@ -633,7 +634,7 @@ __device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ fr, 
 template <int T, int S, bool SEG>
 __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                           int tile, int bb, int bpt) {
-  constexpr int GPB = BLOCK / S, U = 8;
+  constexpr int GPB = BLOCK / S, U = 4;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -741,7 +742,7 @@ __device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_
 template <int T, int S>
 __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                               int tile, int bb, int bpt, uint64_t &live_acc) {
-  constexpr int GPB = BLOCK / S, U = 8;
+  constexpr int GPB = BLOCK / S, U = 4;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
