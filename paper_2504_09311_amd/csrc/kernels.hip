@@ -644,23 +644,39 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
   const int word = tile * T + w;
   const uint64_t actw = SP.act_exp[word] & SP.live_in[word];
   const int32_t *col = P.fwd_col;
-  for (int64_t it = (int64_t)bb * GPB + tid / S; it < n_items; it += (int64_t)bpt * GPB) {
-    int32_t v, eb, ee;
+  // a row's descriptor (vertex, edge range, own vis word); the next row's
+  // is loaded while this one gathers, so its chain of dependent loads
+  // (bin entry, row bounds, vis) is not waited for between rows
+  const int64_t stride = (int64_t)bpt * GPB;
+  const auto load_row = [&](int64_t i, int32_t &rv, int32_t &rb, int32_t &re, uint64_t &ro) {
+    if (i >= n_items) return;
     if (SEG) {
-      v = P.hub_v[it]; eb = P.hub_b[it]; ee = P.hub_e[it];
+      rv = P.hub_v[i]; rb = P.hub_b[i]; re = P.hub_e[i];
     } else {
-      v = items[it]; eb = P.fwd_ptr[v]; ee = P.fwd_ptr[v + 1];
+      rv = items[i]; rb = P.fwd_ptr[rv]; re = P.fwd_ptr[rv + 1];
     }
-    const uint64_t need = actw & ~vis[(size_t)v * T + w];
-    if ((__ballot(need != 0) & gmask) == 0) continue;
-    uint64_t acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask);
+    ro = vis[(size_t)rv * T + w];
+  };
+  int64_t it = (int64_t)bb * GPB + tid / S;
+  int32_t v = 0, eb = 0, ee = 0;
+  uint64_t old = 0;
+  load_row(it, v, eb, ee, old);
+  for (; it < n_items; it += stride) {
+    int32_t vn = 0, ebn = 0, een = 0;
+    uint64_t oldn = 0;
+    load_row(it + stride, vn, ebn, een, oldn);
+    const uint64_t need = actw & ~old;
+    if ((__ballot(need != 0) & gmask) != 0) {
+      uint64_t acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask);
 #pragma unroll
-    for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
-    acc &= need;
-    if (eo == 0 && acc) {
-      if (SEG) atomicOr((unsigned long long *)&nxt[(size_t)v * T + w], acc);
-      else nxt[(size_t)v * T + w] = acc;
+      for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
+      acc &= need;
+      if (eo == 0 && acc) {
+        if (SEG) atomicOr((unsigned long long *)&nxt[(size_t)v * T + w], acc);
+        else nxt[(size_t)v * T + w] = acc;
+      }
     }
+    v = vn; eb = ebn; ee = een; old = oldn;
   }
 }
 
@@ -752,10 +768,24 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
   const uint64_t an = SP.act_new[j], ann = SP.act_nn[j];
   const int32_t *col = P.fwd_col;
   uint8_t *flags = SP.flags_tile + (size_t)tile * P.n;
-  for (int64_t it = (int64_t)bb * GPB + tid / S; it < n_items; it += (int64_t)bpt * GPB) {
-    const int32_t v = items[it], eb = P.fwd_ptr[v], ee = P.fwd_ptr[v + 1];
+  // the next row's descriptor is loaded while this row gathers (as in
+  // pull_rows); the vis word read ahead is the next row's own, which no
+  // other group writes
+  const int64_t stride = (int64_t)bpt * GPB;
+  const auto load_row = [&](int64_t i, int32_t &rv, int32_t &rb, int32_t &re, uint64_t &ro) {
+    if (i >= n_items) return;
+    rv = items[i]; rb = P.fwd_ptr[rv]; re = P.fwd_ptr[rv + 1];
+    ro = P.vis[tb + (size_t)rv * T + w];
+  };
+  int64_t it = (int64_t)bb * GPB + tid / S;
+  int32_t vc = 0, ebc = 0, eec = 0;
+  uint64_t oldc = 0;
+  load_row(it, vc, ebc, eec, oldc);
+  for (; it < n_items; it += stride) {
+    const int32_t v = vc, eb = ebc, ee = eec;
+    const uint64_t old = oldc;
+    load_row(it + stride, vc, ebc, eec, oldc);
     const size_t idx = tb + (size_t)v * T + w;
-    const uint64_t old = P.vis[idx];
     const uint64_t need = actw & ~old;
     uint64_t acc = 0;
     if ((__ballot(need != 0) & gmask) != 0) {
