@@ -590,19 +590,29 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass *__restrict__ Pp, con
 // coalesced, lane i of the group taking edge i (ceil(U / T) loads of S
 // indices), and each thread takes its U indices from those lanes by
 // shuffle; the next round's loads are in flight while this round gathers.
-// Returns the thread's partial OR (not yet combined over eo).
+// The caller loads the first round's indices (col_round at eb) into c, so
+// that it can issue them ahead of the call. Returns the thread's partial OR
+// (not yet combined over eo).
+template <int T, int U>
+constexpr int col_loads() { return (U + T - 1) / T; }
+
+template <int T, int S, int U>
+__device__ __forceinline__ void col_round(const int32_t *__restrict__ col, int32_t e0, int32_t ee, int gl,
+                                          int32_t (&c)[col_loads<T, U>()]) {
+#pragma unroll
+  for (int k = 0; k < col_loads<T, U>(); k++) {
+    const int32_t e = e0 + k * S + gl;
+    c[k] = e < ee ? col[e] : -1;
+  }
+}
+
 template <int T, int S, int U>
 __device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ fr, const int32_t *__restrict__ col,
                                                int32_t eb, int32_t ee, uint64_t need, int gl, int w, int eo,
-                                               uint64_t gmask) {
-  constexpr int E = S / T, NL = (U + T - 1) / T;
+                                               uint64_t gmask, int32_t (&c)[col_loads<T, U>()]) {
+  constexpr int E = S / T, NL = col_loads<T, U>();
   uint64_t acc = 0;
-  int32_t c[NL], cn[NL], x[U];
-#pragma unroll
-  for (int k = 0; k < NL; k++) {
-    const int32_t e = eb + k * S + gl;
-    c[k] = e < ee ? col[e] : -1;
-  }
+  int32_t cn[NL], x[U];
   for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
 #pragma unroll
     for (int u = 0; u < U; u++) x[u] = __shfl(c[u / T], (u % T) * E + eo, S);
@@ -661,13 +671,19 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
   int32_t v = 0, eb = 0, ee = 0;
   uint64_t old = 0;
   load_row(it, v, eb, ee, old);
+  int32_t c[col_loads<T, U>()];
+  col_round<T, S, U>(col, eb, ee, gl, c);
   for (; it < n_items; it += stride) {
     int32_t vn = 0, ebn = 0, een = 0;
     uint64_t oldn = 0;
     load_row(it + stride, vn, ebn, een, oldn);
     const uint64_t need = actw & ~old;
-    if ((__ballot(need != 0) & gmask) != 0) {
-      uint64_t acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask);
+    uint64_t acc = 0;
+    const bool any = (__ballot(need != 0) & gmask) != 0;
+    if (any) acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask, c);
+    // the next row's first column round, issued once its bounds are here
+    col_round<T, S, U>(col, ebn, een, gl, c);
+    if (any) {
 #pragma unroll
       for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
       acc &= need;
@@ -781,6 +797,8 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
   int32_t vc = 0, ebc = 0, eec = 0;
   uint64_t oldc = 0;
   load_row(it, vc, ebc, eec, oldc);
+  int32_t c[col_loads<T, U>()];
+  col_round<T, S, U>(col, ebc, eec, gl, c);
   for (; it < n_items; it += stride) {
     const int32_t v = vc, eb = ebc, ee = eec;
     const uint64_t old = oldc;
@@ -789,10 +807,12 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
     const uint64_t need = actw & ~old;
     uint64_t acc = 0;
     if ((__ballot(need != 0) & gmask) != 0) {
-      acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask);
+      acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask, c);
 #pragma unroll
       for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
     }
+    // the next row's first column round, issued once its bounds are here
+    col_round<T, S, U>(col, ebc, eec, gl, c);
     bool anyf = false, anyneed = false;
     if (eo == 0) {
       const uint64_t fnew = acc & need & an;
