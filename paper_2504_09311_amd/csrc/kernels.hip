@@ -582,58 +582,108 @@ __global__ __launch_bounds__(BLOCK) void k_push(const Pass *__restrict__ Pp, con
   }
 }
 
-// ---- the gather of one row by its group of S = T*E threads: thread (eo, w)
-// ORs word w of the frontier rows of edges eo, eo + E, ... of [eb, ee),
-// rounds of U edges per thread (the pulls use 4: the early-exit test comes
-// after fewer gathers and the round holds fewer registers), and stops once
-// the group has every lane the vertex still misses. The column indices of a round are loaded
-// coalesced, lane i of the group taking edge i (ceil(U / T) loads of S
-// indices), and each thread takes its U indices from those lanes by
-// shuffle; the next round's loads are in flight while this round gathers.
-// The caller loads the first round's indices (col_round at eb) into c, so
-// that it can issue them ahead of the call. Returns the thread's partial OR
-// (not yet combined over eo).
-template <int T, int U>
-constexpr int col_loads() { return (U + T - 1) / T; }
+// ---- the gather of one row by its group of S threads. Inside the gather a
+// thread holds V adjacent words of the row (the pulls use V = 2 for 16-word
+// tiles: 16-byte gathers, so one load instruction moves the rows of twice
+// as many edges; 8-word tiles measured slower with it), LR = T / V threads
+// cover a row and E = S / LR edge slots
+// run side by side: thread (eo, w2) ORs words V*w2 .. V*w2 + V - 1 of the
+// frontier rows of edges eo, eo + E, ... of [eb, ee), rounds of U edges
+// per thread (the pulls use 4: the early-exit test comes after fewer
+// gathers and the round holds fewer registers), and the group stops once
+// it has every lane the vertex still misses. The column indices of a
+// round are loaded coalesced, lane i of the group taking edge i
+// (ceil(U / LR) loads of S indices), and each thread takes its U indices
+// from those lanes by shuffle; the next round's loads are in flight while
+// this round gathers. The caller loads the first round's indices
+// (col_round at eb) into c, so that it can issue them ahead of the call.
+// `need` comes and the result goes in the caller's layout, one word per
+// thread (word gl % T); the result is already combined over the edge slots.
+template <int LR, int U>
+constexpr int col_loads() { return (U + LR - 1) / LR; }
 
-template <int T, int S, int U>
+template <int LR, int S, int U>
 __device__ __forceinline__ void col_round(const int32_t *__restrict__ col, int32_t e0, int32_t ee, int gl,
-                                          int32_t (&c)[col_loads<T, U>()]) {
+                                          int32_t (&c)[col_loads<LR, U>()]) {
 #pragma unroll
-  for (int k = 0; k < col_loads<T, U>(); k++) {
+  for (int k = 0; k < col_loads<LR, U>(); k++) {
     const int32_t e = e0 + k * S + gl;
     c[k] = e < ee ? col[e] : -1;
   }
 }
 
-template <int T, int S, int U>
+template <int T, int V, int S, int U>
 __device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ fr, const int32_t *__restrict__ col,
-                                               int32_t eb, int32_t ee, uint64_t need, int gl, int w, int eo,
-                                               uint64_t gmask, int32_t (&c)[col_loads<T, U>()]) {
-  constexpr int E = S / T, NL = col_loads<T, U>();
-  uint64_t acc = 0;
+                                               int32_t eb, int32_t ee, uint64_t need, int gl, uint64_t gmask,
+                                               int32_t (&c)[col_loads<T / V, U>()]) {
+  static_assert(V == 1 || (V == 2 && T >= 2), "one or two words per thread");
+  constexpr int LR = T / V, E = S / LR, NL = col_loads<LR, U>();
+  const int w = gl % T, w2 = gl % LR, eo = gl / LR;
   int32_t cn[NL], x[U];
-  for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
+  if (V == 1) {
+    uint64_t acc = 0;
+    for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
 #pragma unroll
-    for (int u = 0; u < U; u++) x[u] = __shfl(c[u / T], (u % T) * E + eo, S);
+      for (int u = 0; u < U; u++) x[u] = __shfl(c[u / LR], (u % LR) * E + eo, S);
 #pragma unroll
-    for (int k = 0; k < NL; k++) {
-      const int32_t e = e0 + E * U + k * S + gl;
-      cn[k] = e < ee ? col[e] : -1;
+      for (int k = 0; k < NL; k++) {
+        const int32_t e = e0 + E * U + k * S + gl;
+        cn[k] = e < ee ? col[e] : -1;
+      }
+      // a thread whose word has found every missing lane stops gathering
+      const bool want = (acc & need) != need;
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
+      uint64_t r = acc;
+#pragma unroll
+      for (int off = LR; off < S; off <<= 1) r |= __shfl_xor(r, off);
+      if ((__ballot((r & need) != need) & gmask) == 0) break;
+#pragma unroll
+      for (int k = 0; k < NL; k++) c[k] = cn[k];
     }
-    // a thread whose word has found every missing lane stops gathering
-    const bool want = (acc & need) != need;
 #pragma unroll
-    for (int u = 0; u < U; u++)
-      if (want && x[u] >= 0) acc |= fr[(size_t)x[u] * T + w];
-    uint64_t r = acc;
+    for (int off = LR; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
+    return acc;
+  } else {
+    // this thread's two words' missing lanes, from the threads holding them
+    const uint64_t nx = __shfl(need, 2 * w2, S), ny = __shfl(need, 2 * w2 + 1, S);
+    uint64_t ax = 0, ay = 0;
+    for (int32_t e0 = eb; e0 < ee; e0 += E * U) {
 #pragma unroll
-    for (int off = T; off < S; off <<= 1) r |= __shfl_xor(r, off);
-    if ((__ballot((r & need) != need) & gmask) == 0) break;
+      for (int u = 0; u < U; u++) x[u] = __shfl(c[u / LR], (u % LR) * E + eo, S);
 #pragma unroll
-    for (int k = 0; k < NL; k++) c[k] = cn[k];
+      for (int k = 0; k < NL; k++) {
+        const int32_t e = e0 + E * U + k * S + gl;
+        cn[k] = e < ee ? col[e] : -1;
+      }
+      const bool want = (ax & nx) != nx || (ay & ny) != ny;
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (want && x[u] >= 0) {
+          const u64x2 f = *(const u64x2 *)(fr + (size_t)x[u] * T + 2 * w2);
+          ax |= f.x;
+          ay |= f.y;
+        }
+      uint64_t rx = ax, ry = ay;
+#pragma unroll
+      for (int off = LR; off < S; off <<= 1) {
+        rx |= __shfl_xor(rx, off);
+        ry |= __shfl_xor(ry, off);
+      }
+      if ((__ballot((rx & nx) != nx || (ry & ny) != ny) & gmask) == 0) break;
+#pragma unroll
+      for (int k = 0; k < NL; k++) c[k] = cn[k];
+    }
+#pragma unroll
+    for (int off = LR; off < S; off <<= 1) {
+      ax |= __shfl_xor(ax, off);
+      ay |= __shfl_xor(ay, off);
+    }
+    // back to one word per thread: word w is component w % 2 of thread w / 2
+    const uint64_t bx = __shfl(ax, w >> 1, S), by = __shfl(ay, w >> 1, S);
+    return (w & 1) ? by : bx;
   }
-  return acc;
 }
 
 // ---- pull: a group of S = T*E threads owns one row (or one hub chunk);
@@ -644,7 +694,7 @@ __device__ __forceinline__ uint64_t gather_row(const uint64_t *__restrict__ fr, 
 template <int T, int S, bool SEG>
 __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                           int tile, int bb, int bpt) {
-  constexpr int GPB = BLOCK / S, U = 4;
+  constexpr int GPB = BLOCK / S, U = 4, V = T == 16 ? 2 : 1;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -671,8 +721,8 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
   int32_t v = 0, eb = 0, ee = 0;
   uint64_t old = 0;
   load_row(it, v, eb, ee, old);
-  int32_t c[col_loads<T, U>()];
-  col_round<T, S, U>(col, eb, ee, gl, c);
+  int32_t c[col_loads<T / V, U>()];
+  col_round<T / V, S, U>(col, eb, ee, gl, c);
   for (; it < n_items; it += stride) {
     int32_t vn = 0, ebn = 0, een = 0;
     uint64_t oldn = 0;
@@ -680,12 +730,10 @@ __device__ __forceinline__ void pull_rows(const Pass &P, const Step &SP, const i
     const uint64_t need = actw & ~old;
     uint64_t acc = 0;
     const bool any = (__ballot(need != 0) & gmask) != 0;
-    if (any) acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask, c);
+    if (any) acc = gather_row<T, V, S, U>(fr, col, eb, ee, need, gl, gmask, c);
     // the next row's first column round, issued once its bounds are here
-    col_round<T, S, U>(col, ebn, een, gl, c);
+    col_round<T / V, S, U>(col, ebn, een, gl, c);
     if (any) {
-#pragma unroll
-      for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
       acc &= need;
       if (eo == 0 && acc) {
         if (SEG) atomicOr((unsigned long long *)&nxt[(size_t)v * T + w], acc);
@@ -774,7 +822,7 @@ __device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_
 template <int T, int S>
 __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                               int tile, int bb, int bpt, uint64_t &live_acc) {
-  constexpr int GPB = BLOCK / S, U = 4;
+  constexpr int GPB = BLOCK / S, U = 4, V = T == 16 ? 2 : 1;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
@@ -797,8 +845,8 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
   int32_t vc = 0, ebc = 0, eec = 0;
   uint64_t oldc = 0;
   load_row(it, vc, ebc, eec, oldc);
-  int32_t c[col_loads<T, U>()];
-  col_round<T, S, U>(col, ebc, eec, gl, c);
+  int32_t c[col_loads<T / V, U>()];
+  col_round<T / V, S, U>(col, ebc, eec, gl, c);
   for (; it < n_items; it += stride) {
     const int32_t v = vc, eb = ebc, ee = eec;
     const uint64_t old = oldc;
@@ -806,13 +854,9 @@ __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, con
     const size_t idx = tb + (size_t)v * T + w;
     const uint64_t need = actw & ~old;
     uint64_t acc = 0;
-    if ((__ballot(need != 0) & gmask) != 0) {
-      acc = gather_row<T, S, U>(fr, col, eb, ee, need, gl, w, eo, gmask, c);
-#pragma unroll
-      for (int off = T; off < S; off <<= 1) acc |= __shfl_xor(acc, off);
-    }
+    if ((__ballot(need != 0) & gmask) != 0) acc = gather_row<T, V, S, U>(fr, col, eb, ee, need, gl, gmask, c);
     // the next row's first column round, issued once its bounds are here
-    col_round<T, S, U>(col, ebc, eec, gl, c);
+    col_round<T / V, S, U>(col, ebc, eec, gl, c);
     bool anyf = false, anyneed = false;
     if (eo == 0) {
       const uint64_t fnew = acc & need & an;
