@@ -113,10 +113,12 @@ def byte_model(st: dict, n: int, kernel: str, launches: float = 0.0, fused: bool
     return 0.0
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, kernel_name: str | None = None):
     """HBM bytes per launch of `kernel` on `workload` from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when there is none or
-    the kernel's source file changed since the counters were taken."""
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when there is none, the
+    kernel's source file changed since the counters were taken, or the
+    summary was taken on another kernel of the class than `kernel_name` (the
+    pull class runs as k_pull<T> or, finalize fused, as k_pull_fin<T>)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
@@ -132,6 +134,8 @@ def measured_traffic(kernel: str, workload: str):
         return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    if kernel_name and fields.get("kernel_name", kernel_name) != kernel_name:
         return None
     return int(float(fields["traffic_bytes_per_launch"]))
 
@@ -580,7 +584,10 @@ def main():
             per_launch_bytes = modeled_dom * args.steps / launches
             avg_s = total_ms / 1e3 / launches
             achieved = per_launch_bytes / avg_s / 1e9
-            traffic = measured_traffic(dom, args.workload)
+            kname = None
+            if dom == "pull":
+                kname = ("k_pull_fin<%d>" if st["fused_pull"] else "k_pull<%d>") % st["tile_words"]
+            traffic = measured_traffic(dom, args.workload, kname)
             roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                             frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                             bytes_per_launch=int(per_launch_bytes), avg_launch_us=round(avg_s * 1e6, 3),
