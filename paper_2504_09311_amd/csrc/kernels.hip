@@ -444,7 +444,7 @@ __global__ __launch_bounds__(BLOCK) void k_finalize(const Pass *__restrict__ Pp,
             }
           }
           if (S.write_next) {
-            __builtin_nontemporal_store(fnew, &frn[idx]);
+            if (!S.next_in_plane) __builtin_nontemporal_store(fnew, &frn[idx]);
             lacc |= fnew;
             anyneed[u] |= ann & ~nv;
           }
@@ -815,7 +815,7 @@ __device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_
       *pp = *pp | fnew;
     }
   }
-  if (S.write_next) __builtin_nontemporal_store(fnew, &S.fr_next[idx]);
+  if (S.write_next && !S.next_in_plane) __builtin_nontemporal_store(fnew, &S.fr_next[idx]);
   return nv;
 }
 
@@ -885,7 +885,7 @@ __device__ __forceinline__ void fin_zero_rows(const Pass &P, const Step &SP, int
     const size_t idx = (size_t)tile * P.n * T + (size_t)v * T + w;
     for (int b = 0; b < P.B; b++)
       if (first_store && nl == (1 << b)) P.planes[b * P.pstride + idx] = 0ull;
-    if (SP.write_next) __builtin_nontemporal_store(0ull, &SP.fr_next[idx]);
+    if (SP.write_next && !SP.next_in_plane) __builtin_nontemporal_store(0ull, &SP.fr_next[idx]);
     if (w == 0) flags[v] = 0;
   }
 }

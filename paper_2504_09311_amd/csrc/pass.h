@@ -115,6 +115,9 @@ struct Step {
   uint64_t *live_out;        // [Wp]
   int32_t build_list;        // write the frontier list (a following push reads it)
   int32_t write_next;        // write fr_next and live_out
+  int32_t next_in_plane;     // the next frontier is distance plane 0 (level 1 of a batched pass, where
+                             // plane 0 is stored outright): fr_next is not written, the next step's
+                             // fr_cur is the plane
   int32_t clear_planes;      // clear the distance planes when a word starts; otherwise every
                              // word reaches level 2^b for every plane b, where b is stored
   int32_t fused;             // a pulled level is finalized by the pull itself (every word's

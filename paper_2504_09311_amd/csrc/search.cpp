@@ -197,6 +197,13 @@ kws_status enqueue_pass(kws_graph *g, const std::vector<QIn> &qs, int qa, int qb
     S.st_out = stats + (size_t)(lv + 1) * STAT_WORDS;
     S.live_out = live + (size_t)(lv + 1) * Wp;
     S.build_list = S.write_next = lv + 1 < D;
+    // level 1's frontier equals distance plane 0, which this step stores
+    // outright for every vertex-word (planes are not cleared per word in a
+    // batched pass): the next step gathers from the plane and the frontier
+    // buffer is not written. Level 2 stores plane 1 outright, so nothing
+    // writes plane 0 while it is gathered.
+    S.next_in_plane = lv == 0 && S.write_next && B >= 1;
+    if (lv == 1 && D >= 2 && B >= 1) S.fr_cur = P.planes;
     S.fused = lv >= 0 && fused;
     S.flags_tile = fused ? E.flags_tile.as<uint8_t>() : nullptr;
     S.dev = pw.dev<Step>(E, o_steps) + (lv + 1);
