@@ -1546,22 +1546,17 @@ __global__ __launch_bounds__(AB) void k_answer(const Pass *__restrict__ Pp) {
         best = block_min(mine, &s_best);
       } else {
         // rows are sorted by neighbour id, so the qualifying neighbours of
-        // the first round that has any include the smallest-id one; most
-        // walks stop in their first round of AB neighbours, so rounds are
-        // not made longer
-        constexpr int U = 1;
-        for (int32_t eb = e0; eb < e1; eb += AB * U) {
-          int32_t y[U], mine = 0x7fffffff;
-#pragma unroll
-          for (int u = 0; u < U; u++) {
-            const int32_t e = eb + u * AB + tid;
-            y[u] = e < e1 ? P.fwd_col[e] : -1;
-          }
-#pragma unroll
-          for (int u = 0; u < U; u++)
-            if (y[u] >= 0 && ((P.vis[tb + (size_t)y[u] * T + w] >> bit) & 1ull) &&
-                lane_dist(P, tb + (size_t)y[u] * T + w, bit) == d - 1)
-              mine = min(mine, y[u]);
+        // the first round that has any include the smallest-id one. Most
+        // walks stop in their first round, and every neighbour checked
+        // costs up to three random loads, so the first round takes 64
+        // neighbours (one wavefront) and the later ones AB
+        for (int32_t eb = e0, rw = 64; eb < e1; eb += rw, rw = AB) {
+          int32_t mine = 0x7fffffff;
+          const int32_t e = eb + tid;
+          const int32_t y = tid < rw && e < e1 ? P.fwd_col[e] : -1;
+          if (y >= 0 && ((P.vis[tb + (size_t)y * T + w] >> bit) & 1ull) &&
+              lane_dist(P, tb + (size_t)y * T + w, bit) == d - 1)
+            mine = y;
           best = block_min(mine, &s_best);
           if (best != 0x7fffffff) break;
         }
