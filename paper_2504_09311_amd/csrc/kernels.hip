@@ -822,7 +822,10 @@ __device__ __forceinline__ uint64_t fin_word(const Pass &P, const Step &S, size_
 template <int T, int S>
 __device__ __forceinline__ void pull_fin_rows(const Pass &P, const Step &SP, const int32_t *items, int64_t n_items,
                                               int tile, int bb, int bpt, uint64_t &live_acc) {
-  constexpr int GPB = BLOCK / S, U = 4, V = T == 16 ? 2 : 1;
+  // rounds of 2 edges per thread when a thread gathers 16 bytes: in the
+  // fused pull (state beyond the Infinity Cache) that measured faster than
+  // 4; the unfused pull, run from cache-resident state, keeps 4
+  constexpr int GPB = BLOCK / S, V = T == 16 ? 2 : 1, U = V == 2 ? 2 : 4;
   const int tid = threadIdx.x, gl = tid % S, w = gl % T, eo = gl / T, lane = tid & 63;
   const uint64_t gmask = group_bits(lane, S);
   const size_t tb = (size_t)tile * P.n * T;
