@@ -58,6 +58,7 @@ struct QueryTables {
   std::vector<uint8_t> bits;
   int64_t nhist = 0, ncand = 0, nslots = 0, nkd = 0, nedge = 0;
   int32_t chunks = 1, CH = 64;
+  int32_t hist_split = 0, hist_words = 0;   // score's packed LDS histogram (see k_score)
   bool hist_lds = true, te_lds = true;
   kws_status build(const kws_graph *g, const std::vector<const QIn *> &qs, const std::vector<Placed> &pl, int Wp);
 };

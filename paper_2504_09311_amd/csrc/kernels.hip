@@ -1037,7 +1037,14 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
   const Pass &P = *Pp;
   extern __shared__ uint64_t s_dyn[];
   uint64_t *s_te = s_dyn;                                   // [nq] in word order (count_te)
-  int32_t *s_hist = (int32_t *)(s_dyn + (TE ? P.nq : 0));   // [nhist]
+  // the chunk histogram in LDS: two copies (a lane adds to the copy of its
+  // parity, so lanes with equal scores meet half as often on one word), each
+  // of hist_words words holding two 16-bit bins: bins below hist_split in
+  // the low halves, the others (bin - hist_split) in the high halves; a
+  // query's bins lie in one half. A bin counts at most the 128 lanes of one
+  // parity in a block round, so a low half never carries into the high one
+  uint32_t *s_hist = (uint32_t *)(s_dyn + (TE ? P.nq : 0));   // [2][hist_words]
+  const int HW = P.hist_words, HS = P.hist_split;
   typedef const __attribute__((address_space(4))) QWord *QWordC;
   typedef const __attribute__((address_space(4))) int32_t *I32C;
   const QWordC qw = (QWordC)P.qw;
@@ -1050,7 +1057,7 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
   for (int64_t bid = blockIdx.x; bid < (int64_t)P.chunks * split; bid += gridDim.x) {
     const int c = (int)(bid / split), part = (int)(bid % split);
     if (L)
-      for (int i = tid; i < P.nhist; i += BLOCK) s_hist[i] = 0;
+      for (int i = tid; i < 2 * HW; i += BLOCK) s_hist[i] = 0;
     __syncthreads();
     const int64_t cend = min((int64_t)P.n, (int64_t)(c + 1) * P.CH);
     const int64_t v = (int64_t)c * P.CH + (int64_t)part * BLOCK + tid;
@@ -1196,8 +1203,12 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
               int sc = 0;
 #pragma unroll
               for (int b = 0; b < PB; b++) sc += __popcll(pl[b][w] & m) << b;
-              if (L) atomicAdd(&s_hist[hoff + sc], 1);
-              else atomicAdd(&P.hist[(size_t)c * P.nhist + hoff + sc], 1);
+              if (L) {
+                const bool hi = hoff >= HS;      // per query: scalar
+                atomicAdd(&s_hist[(lane & 1) * HW + (hi ? hoff - HS : hoff) + sc], hi ? 0x10000u : 1u);
+              } else {
+                atomicAdd(&P.hist[(size_t)c * P.nhist + hoff + sc], 1);
+              }
             }
           }
         }
@@ -1206,8 +1217,12 @@ __global__ __launch_bounds__(BLOCK) void k_score(const Pass *__restrict__ Pp, co
     if (FIN && anyf) { nf_acc++; mf_acc += (uint64_t)(P.rev_ptr[v + 1] - P.rev_ptr[v]); }
     __syncthreads();
     if (L)
-      for (int i = tid; i < P.nhist; i += BLOCK)
-        if (s_hist[i]) atomicAdd(&P.hist[(size_t)c * P.nhist + i], s_hist[i]);
+      for (int i = tid; i < HW; i += BLOCK) {
+        const uint32_t a = s_hist[i], b = s_hist[HW + i];
+        const int32_t lo = (int32_t)((a & 0xFFFFu) + (b & 0xFFFFu)), hi = (int32_t)((a >> 16) + (b >> 16));
+        if (lo && i < HS) atomicAdd(&P.hist[(size_t)c * P.nhist + i], lo);
+        if (hi && HS + i < P.nhist) atomicAdd(&P.hist[(size_t)c * P.nhist + HS + i], hi);
+      }
     __syncthreads();
   }
   if (L && TE) {
@@ -1646,7 +1661,7 @@ inline int64_t launch_size(const Pass &P, int64_t x) {
 
 inline size_t score_lds(const Pass &P) {
   return P.hist_lds ? (size_t)launch_size(P, (int64_t)((P.count_te ? (size_t)P.nq * 8 : 0) +
-                                                      sizeof(int32_t) * (size_t)P.nhist))
+                                                      8 * (size_t)P.hist_words))
                     : 0;
 }
 

@@ -37,6 +37,7 @@ struct Pass {
   int32_t n, T, tiles, Wp, B, nq, n_lanes;
   int32_t W;                         // words in use; words W..Wp-1 pad the last tile (no lane, no query)
   int32_t chunks, CH, nhist, hist_lds, te_lds;
+  int32_t hist_split, hist_words;    // score's LDS histogram: first bin of the high halves, words per copy
   int32_t force_dir, count_te;
   float alpha;
   int64_t total_seeds, n_hub, total_slots, total_kd;

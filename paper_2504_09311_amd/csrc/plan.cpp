@@ -191,9 +191,15 @@ kws_status QueryTables::build(const kws_graph *g, const std::vector<const QIn *>
   chunks = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n + 1023) / 1024, hist_cap));
   CH = (int)align_up((size_t)((n + chunks - 1) / chunks), 64);
   chunks = (n + CH - 1) / CH;
-  // the score step keeps one chunk's histogram (and, counting te, a sum
-  // per query) in at most 64 KB of LDS
-  hist_lds = (size_t)nq * 8 + (size_t)nhist * 4 <= 65536;
+  // the score step's LDS histogram packs two 16-bit bins per word: the
+  // queries from the first whose bins start at or past the middle go to
+  // the high halves, so that each query's bins lie in one half
+  hist_split = (int32_t)nhist;
+  for (int i = 0; i < nq; i++)
+    if (2 * (int64_t)hoff[i] >= nhist) { hist_split = hoff[i]; break; }
+  hist_words = std::max<int32_t>(hist_split, (int32_t)nhist - hist_split);
+  // two copies of it (and, counting te, a sum per query) in at most 64 KB
+  hist_lds = (size_t)nq * 8 + (size_t)hist_words * 8 <= 65536;
   te_lds = hist_lds;
   if ((size_t)chunks * (size_t)nhist > (size_t)INT32_MAX) return fail(KWS_EOVERFLOW, "histogram too large");
   return KWS_OK;
@@ -331,6 +337,8 @@ void fill_pass(Pass &P, kws_graph *g, Engine &E, int T, int tiles, int B, const 
   P.CH = Q.CH;
   P.nhist = (int32_t)Q.nhist;
   P.hist_lds = Q.hist_lds;
+  P.hist_split = Q.hist_split;
+  P.hist_words = Q.hist_words;
   P.te_lds = Q.te_lds;
   P.force_dir = g->opt.direction;
   P.count_te = g->opt.count_te > 0;
